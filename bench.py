@@ -1,0 +1,228 @@
+"""Throughput of the fused D2Q37 time step on one MI355X.
+
+Workload (one line of JSON on stdout): a 2048 x 2048 periodic lattice, shear
+wave u_x = 0.05 sin(2 pi y / LY) plus 1e-4 seeded noise, tau = 0.8, FP64
+populations in the CAoSoA layout (the layout the paper's Table 1 uses),
+propagate and collide fused in one kernel with ping-pong buffers. `value` is million lattice updates per second (MLUPS)
+over K timed steps with the state resident in HBM.
+
+The same line carries the other forms of the step measured on the same GPU
+(FP32-shifted and FP16-shifted storage with their per-field error against
+the FP64 run, the AoS/CSoA/CAoSoA layouts, the split propagate + collide
+path), a roofline object for the dominant kernel and the CPU oracle timed on
+the host cores.
+"""
+from __future__ import annotations
+
+import argparse
+import glob
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "MLUPS fused step, FP64 vs FP32-shifted/surrogate at stated err; % HBM roof"
+LX = LY = 2048
+TAU = 0.8
+PROFILE_TRAFFIC = os.path.join(ROOT, "profiles", "traffic.json")
+
+
+def source_digest() -> str:
+    h = hashlib.sha256()
+    for path in sorted(glob.glob(os.path.join(ROOT, "paper_1804_01918_amd", "csrc", "*"))):
+        with open(path, "rb") as fh:
+            h.update(os.path.basename(path).encode())
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def timed_steps(lat, torch, nsteps: int, split: bool = False) -> float:
+    """Seconds for nsteps, HIP events on the lattice's stream."""
+    stream = lat.stream
+    start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    start.record(stream)
+    if split:
+        for _ in range(nsteps):
+            lat.propagate()
+            lat.collide()
+    else:
+        lat.step(nsteps)
+    stop.record(stream)
+    stop.synchronize()
+    torch.cuda.synchronize()
+    return start.elapsed_time(stop) / 1e3
+
+
+def field_errors(ref, got):
+    """Per-field max and rms absolute error against the FP64 run."""
+    names = ("rho", "ux", "uy", "T")
+    out = {}
+    for n, a, b in zip(names, ref, got):
+        d = (b - a)
+        out[n] = {"max_abs": float(d.abs().max()), "rms": float(d.pow(2).mean().sqrt())}
+    return out
+
+
+def copy_bandwidth(torch, lb, nbytes: int, reps: int = 20) -> float:
+    src = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+    dst = torch.empty_like(src)
+    src.fill_(1)
+    lb.device_copy(dst, src)
+    stream = torch.cuda.current_stream()
+    start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    start.record(stream)
+    for _ in range(reps):
+        lb.device_copy(dst, src)
+    stop.record(stream)
+    stop.synchronize()
+    dt = start.elapsed_time(stop) / 1e3 / reps
+    return 2 * nbytes / dt / 1e9
+
+
+def traffic_entry(kernel: str, per_launch_sites: int):
+    """HBM bytes per launch from the committed rocprofv3 counter summary, if
+    it was taken on the current kernel sources; else None."""
+    if not os.path.exists(PROFILE_TRAFFIC):
+        return None
+    with open(PROFILE_TRAFFIC) as fh:
+        rec = json.load(fh)
+    if rec.get("source_digest") != source_digest():
+        return None
+    k = rec.get("kernels", {}).get(kernel)
+    if not k or k.get("sites") != per_launch_sites:
+        return None
+    return k.get("hbm_bytes_per_launch")
+
+
+def cpu_baseline(seconds_target: float = 12.0):
+    """The FP64 oracle (plain C, one thread) on a bounded sample of the same
+    workload: a 512 x 512 window of the shear-wave state."""
+    from oracle import lbm
+    from paper_1804_01918_amd import inputs
+    lx, ly = 512, 512
+    f = lbm.init(*inputs.shear_wave(lx, ly, seed=0))
+    t0 = time.perf_counter()
+    f = lbm.run(f, TAU, 1)
+    one = time.perf_counter() - t0
+    steps = max(1, int(seconds_target / max(one, 1e-3)))
+    t0 = time.perf_counter()
+    lbm.run(f, TAU, steps)
+    dt = time.perf_counter() - t0
+    return {"value": lx * ly * steps / dt / 1e6, "unit": "MLUPS", "cores": 1, "kind": "oracle",
+            "sample": f"FP64 oracle, {lx}x{ly} shear-wave lattice, {steps} steps, 1 thread, {dt:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=1000)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--variant-steps", type=int, default=200)
+    ap.add_argument("--no-variants", action="store_true")
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--only", default=None, help="precision:layout[:split] to time alone")
+    ap.add_argument("--copy-bytes", type=int, default=0,
+                    help="only run the library's copy kernel on buffers of this size (counter calibration)")
+    ap.add_argument("--copy-reps", type=int, default=5)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py: this build measures one GPU; --gpus {args.gpus} is not supported "
+              "(the lattice is not sharded across GPUs)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_1804_01918_amd import inputs, lb
+    from paper_1804_01918_amd.roofline import HBM_PEAK_GBS, bytes_per_site
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    if args.copy_bytes:
+        gbs = copy_bandwidth(torch, lb, args.copy_bytes, reps=args.copy_reps)
+        print(json.dumps({"copy_bytes": args.copy_bytes, "reps": args.copy_reps, "GB/s": gbs}))
+        return
+    fields = [torch.from_numpy(a).cuda() for a in inputs.shear_wave(LX, LY, seed=0)]
+    nsites = LX * LY
+
+    def run(prec, layout, steps, warmup, split=False, keep=False):
+        lat = lb.Lattice(LX, LY, TAU, fields, precision=prec, layout=layout, audit=True)
+        if split:
+            for _ in range(warmup):
+                lat.propagate()
+                lat.collide()
+        else:
+            lat.step(warmup)
+        dt = timed_steps(lat, torch, steps, split=split)
+        mom = lat.moments() if keep else None
+        lat.close()
+        del lat
+        torch.cuda.empty_cache()
+        return dt, mom
+
+    if args.only:
+        parts = args.only.split(":")
+        dt, _ = run(parts[0], parts[1], args.steps, args.warmup, split=len(parts) > 2)
+        print(json.dumps({"only": args.only, "mlups": nsites * args.steps / dt / 1e6,
+                          "ms_per_step": dt / args.steps * 1e3}))
+        return
+
+    # Headline: FP64 CAoSoA fused.
+    dt, ref_mom = run("f64", "caosoa", args.steps, args.warmup, keep=True)
+    mlups = nsites * args.steps / dt / 1e6
+    t_launch = dt / args.steps
+    alg_bytes = bytes_per_site("f64", fused=True) * nsites
+    achieved = alg_bytes / t_launch / 1e9
+    traffic = traffic_entry("k_step_f64_caosoa", nsites)
+
+    out = {
+        "metric": METRIC, "value": mlups, "unit": "MLUPS", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": t_launch * 1e3, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": "D2Q37 2048x2048 periodic shear wave (u_x=0.05 sin(2 pi y/LY) + 1e-4 noise), "
+                               "FP64 populations, CAoSoA layout, fused propagate+collide, tau=0.8",
+                   "lattice": [LX, LY], "precision": "f64", "layout": "caosoa", "fused": True, "tau": TAU,
+                   "audit": "FP64 mass/momentum/energy sums fused into the last timed step"},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+                     "kernel": "k_step<PrecF64, Layout<CAoSoA>> (fused propagate+collide)",
+                     "algorithmic_bytes_per_site": bytes_per_site("f64", fused=True)},
+    }
+
+    if not args.no_variants:
+        variants = {}
+        vs = args.variant_steps
+        for prec in ("f32s", "f16s"):
+            dtv, mom = run(prec, "caosoa", args.steps, args.warmup, keep=True)
+            m = nsites * args.steps / dtv / 1e6
+            variants[f"{prec}_caosoa_fused"] = {
+                "compensated_moment_sums": prec == "f32s",
+                "mlups": m, "ms_per_step": dtv / args.steps * 1e3,
+                "hbm_frac": m * 1e6 * bytes_per_site(prec[:3]) / (HBM_PEAK_GBS * 1e9),
+                "error_vs_f64_after_steps": args.steps + args.warmup,
+                "field_error_vs_f64": field_errors(ref_mom, mom)}
+        for layout in ("soa", "aos", "csoa"):
+            dtv, _ = run("f64", layout, vs, args.warmup)
+            m = nsites * vs / dtv / 1e6
+            variants[f"f64_{layout}_fused"] = {"mlups": m, "hbm_frac": m * 1e6 * 592 / (HBM_PEAK_GBS * 1e9)}
+        for layout in ("soa", "caosoa"):
+            dtv, _ = run("f64", layout, vs, args.warmup, split=True)
+            m = nsites * vs / dtv / 1e6
+            variants[f"f64_{layout}_split"] = {"mlups": m, "hbm_frac": m * 1e6 * 1184 / (HBM_PEAK_GBS * 1e9)}
+        cb = copy_bandwidth(torch, lb, alg_bytes // 2)
+        variants["copy_kernel_gbs"] = cb
+        out["roofline"]["frac_of_copy"] = achieved / cb
+        out["variants"] = variants
+
+    if not args.no_cpu:
+        out["cpu_baseline"] = cpu_baseline()
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,160 @@
+/*
+ * lb.h - C ABI of libd2q37: one D2Q37 Lattice Boltzmann time step on an
+ * AMD Instinct MI355X (gfx950).
+ *
+ * The problem (paper: Calore, Gabbana, Schifano, Tripiccione, "Early
+ * experience on using Knights Landing processors for Lattice Boltzmann
+ * applications", Section 3 and Listing 1):
+ *   - a periodic LX x LY lattice with 37 populations per site, each moving up
+ *     to three lattice points per step (the D2Q37 model);
+ *   - two copies of the populations; a time step is propagate (every
+ *     population moves to the site its hop points at) followed by collide
+ *     (per site: density rho, velocity u and temperature T, the model's
+ *     equilibrium with perfect-gas pressure p = rho T, and relaxation);
+ *   - throughput counted in lattice updates per second.
+ *
+ * Conventions for every call:
+ *   - Return 0 (LB_OK) on success or a negative LB_E* code; lb_last_error()
+ *     gives a message. No C++ exception crosses this interface.
+ *   - Device pointers are plain HIP device addresses (for example from
+ *     torch.empty(..., device="cuda").data_ptr()). Every device call is
+ *     asynchronous on the context's stream; calls that return host data
+ *     (lb_audit, lb_last_error) synchronise that stream. A device fault
+ *     surfaces at the next synchronising call as LB_EDEVICE.
+ *   - Ownership: the caller owns every device buffer (the two population
+ *     buffers and the scratch area) and must keep them alive until
+ *     lb_destroy. The library allocates no device memory; it allocates and
+ *     frees only its host-side context.
+ *   - Units: velocities and temperature are in thermal units (velocity in
+ *     units of the reference thermal speed, T relative to the reference
+ *     temperature); the lattice hop c_p corresponds to the thermal velocity
+ *     xi_p = r c_p with r = 1.19697977... (see lb_model_constants).
+ *   - Canonical interchange layout of populations: FP64 f[p][x][y], y
+ *     contiguous (site index = LY*x + y, as in Listing 1); p follows the
+ *     population order of lb_model_constants. Fields are FP64 [x][y].
+ *   - A context is not thread-safe; distinct contexts are independent.
+ */
+#ifndef LIBD2Q37_LB_H
+#define LIBD2Q37_LB_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define LB_Q 37
+
+enum {
+    LB_OK = 0,
+    LB_EINVAL = -1,        /* bad extent, tau, pointer, alignment or size */
+    LB_EDEVICE = -2,       /* a HIP call failed; see lb_last_error */
+    LB_EUNSUPPORTED = -3,  /* combination of options not provided */
+    LB_ENONFINITE = -4     /* the audit found NaN or Inf in the lattice totals */
+};
+
+/* Storage precision of the populations (the computation follows it):
+ *   LB_FP64         f in FP64, FP64 arithmetic.
+ *   LB_FP32_SHIFTED g = f - w_p (deviation from the rest state rho0 = 1)
+ *                   in FP32; FP32 arithmetic; moments with compensated sums
+ *                   unless lb_config.compensated = 0.
+ *   LB_FP16_SHIFTED g * s_p in FP16, s_p an exact power of two near 1/w_p;
+ *                   FP32 arithmetic. */
+typedef enum { LB_FP64 = 0, LB_FP32_SHIFTED = 1, LB_FP16_SHIFTED = 2 } lb_precision;
+
+/* Memory layout of the populations (paper, Section 4, Fig. 2); VL is 128
+ * bytes of storage (16 FP64, 32 FP32, 64 FP16 values):
+ *   LB_SOA    [p][x][y]
+ *   LB_AOS    [x][y][p]
+ *   LB_CSOA   [p][x][i][k]   y = i + k*(LY/VL); needs LY % VL == 0
+ *   LB_CAOSOA [x][i][p][k]   same clusters, the 37 of a site index adjacent */
+typedef enum { LB_SOA = 0, LB_AOS = 1, LB_CSOA = 2, LB_CAOSOA = 3 } lb_layout;
+
+typedef struct {
+    int32_t lx, ly;       /* periodic extents, >= 1 each, lx*ly < 2^31 */
+    double tau;           /* BGK relaxation time in steps, > 0.5 */
+    int32_t precision;    /* lb_precision */
+    int32_t layout;       /* lb_layout */
+    int32_t compensated;  /* FP32 moment sums of the shifted precisions: 1 = compensated
+                             (TwoSum cascades), 0 = plain; FP64 ignores it */
+    int32_t audit;        /* nonzero: lb_step fuses the FP64 audit sums into its last step */
+    void *buf[2];         /* device, lb_buffer_bytes() each, 256-byte aligned */
+    void *scratch;        /* device, >= lb_scratch_bytes(), 256-byte aligned */
+    size_t scratch_bytes; /* size of scratch in bytes */
+    void *stream;         /* hipStream_t to launch on; NULL = the null stream */
+} lb_config;
+
+typedef struct lb_ctx lb_ctx;
+
+/* Bytes of one population buffer; 0 if the combination is invalid. */
+size_t lb_buffer_bytes(int32_t lx, int32_t ly, int32_t precision, int32_t layout);
+
+/* Bytes of scratch a context of this lattice needs (audit partial sums). */
+size_t lb_scratch_bytes(int32_t lx, int32_t ly);
+
+/* Create a context and set the populations of buf[0] to the equilibrium of
+ * the FP64 device fields rho, ux, uy, T ([lx][ly] each). On error *out is
+ * NULL. Validates: extents, tau > 0.5, precision/layout, LY % VL for the
+ * clustered layouts, non-NULL 256-byte-aligned buffers, scratch size. */
+int lb_init(lb_ctx **out, const lb_config *cfg, const double *rho, const double *ux,
+            const double *uy, const double *T);
+
+/* Propagate (paper, Section 3; Listing 1): every population p at site s is
+ * replaced by the one at s - c_p (pull gather, periodic), copied bit for bit
+ * into the other buffer, which then becomes current. */
+int lb_propagate(lb_ctx *ctx);
+
+/* Collide (paper, Section 3): per site, moments, equilibrium and BGK
+ * relaxation f <- f - (f - f_eq)/tau, in place on the current buffer. */
+int lb_collide(lb_ctx *ctx);
+
+/* nsteps time steps, each propagate then collide fused in one kernel that
+ * reads the current buffer and writes the other (ping-pong). Bit-identical
+ * to nsteps x (lb_propagate; lb_collide). nsteps = 0 is a no-op. */
+int lb_step(lb_ctx *ctx, int32_t nsteps);
+
+/* Macroscopic fields of the current state, in FP64 (device [lx][ly] each):
+ * rho = sum f, rho u = sum f xi, rho (|u|^2 + 2 T) = sum f |xi|^2. */
+int lb_moments(lb_ctx *ctx, double *rho, double *ux, double *uy, double *T);
+
+/* Current populations in the canonical FP64 layout (device [37][lx][ly]);
+ * shifted storage is returned as f = w_p + g. */
+int lb_get_populations(lb_ctx *ctx, double *f);
+
+/* Replace the current populations from canonical FP64 (device [37][lx][ly]);
+ * shifted storage keeps g = f - w_p rounded to nearest even. */
+int lb_set_populations(lb_ctx *ctx, const double *f);
+
+/* Lattice totals in FP64 on the host: out = {mass, x-momentum, y-momentum,
+ * energy = 1/2 sum f |xi|^2}, summed in a fixed order (run to run
+ * reproducible). Uses the sums fused into the last lb_step when they are
+ * still current, else reduces the current buffer. Synchronises the stream.
+ * Returns LB_ENONFINITE (with out filled) if any total is NaN or Inf. */
+int lb_audit(lb_ctx *ctx, double out[4]);
+
+/* Index (0 or 1) of the buffer holding the current state. */
+int lb_current_buffer(const lb_ctx *ctx);
+
+/* Number of time steps applied so far (propagate + collide pairs count as one
+ * after the collide). */
+int64_t lb_steps_done(const lb_ctx *ctx);
+
+void lb_destroy(lb_ctx *ctx);
+
+const char *lb_strerror(int code);
+const char *lb_last_error(const lb_ctx *ctx);
+
+/* The library's model constants (host): r, the weights w[37] and the hops
+ * c[37][2] in the library's population order. Any pointer may be NULL. */
+int lb_model_constants(double *r, double *w, int32_t *c);
+
+/* Streaming device copy of `bytes` (multiple of 16, 16-byte aligned
+ * pointers) on `stream`: the reference for achievable HBM bandwidth. */
+int lb_copy(void *dst, const void *src, size_t bytes, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LIBD2Q37_LB_H */

@@ -1,0 +1,302 @@
+// HIP kernels of the D2Q37 step: init, propagate, collide, the fused step,
+// FP64 readouts (moments, canonical populations) and the FP64 audit.
+#pragma once
+
+#include "lb_collide.hpp"
+
+namespace d2q37 {
+
+constexpr int BLOCK = 256;
+
+// ---- FP64 conversions of stored values ------------------------------------
+
+// Stored value -> FP64 f (plain) or g (shifted). Exact for every precision.
+template <class P>
+__device__ inline double load_f64(const typename P::T* a, int p)
+{
+    if constexpr (P::kind == PREC_F16S)
+        return (double)__half2float(__ushort_as_half(*a)) / (double)S16[shell_of_c2(c2_of(p))];
+    else
+        return (double)*a;
+}
+
+// Round an FP64 value to nearest-even FP16 without double rounding: first to
+// FP32 with round-to-odd (truncate, then set the last bit if inexact), which
+// keeps enough bits for the final FP32 -> FP16 rounding to be correct.
+__device__ inline uint16_t f64_to_f16_rne(double x)
+{
+    float f = __double2float_rz(x);
+    if ((double)f != x && x == x) {
+        uint32_t b = __float_as_uint(f);
+        b |= 1u;
+        f = __uint_as_float(b);
+    }
+    return __half_as_ushort(__float2half_rn(f));
+}
+
+// FP64 f (plain) or g (shifted) -> stored value, rounding to nearest even.
+template <class P>
+__device__ inline void store_from_f64(typename P::T* a, int p, double v)
+{
+    if constexpr (P::kind == PREC_F16S)
+        *a = f64_to_f16_rne(v * (double)S16[shell_of_c2(c2_of(p))]);
+    else
+        *a = (typename P::T)v;
+}
+
+// The compute value as it will read back after storage (FP16 rounds).
+template <class P>
+__device__ inline double stored_as_f64(typename P::C v, int p)
+{
+    if constexpr (P::kind == PREC_F16S) {
+        const float s = S16[shell_of_c2(c2_of(p))];
+        return (double)__half2float(__float2half_rn(v * s)) / (double)s;
+    } else {
+        return (double)v;
+    }
+}
+
+// ---- FP64 audit ------------------------------------------------------------
+// Per site: {sum v, R sum cx v, R sum cy v, R^2/2 sum |c|^2 v}, i.e. mass,
+// momentum and energy (1/2 sum f xi^2) of f, or of g for shifted storage
+// (the constant part 1, 0, 0, 1 per site is added at finalisation).
+__device__ inline void audit_site(const double (&d)[Q], double (&acc)[4])
+{
+    double m = 0.0, jx = 0.0, jy = 0.0, e = 0.0;
+#pragma unroll
+    for (int p = 0; p < Q; ++p) {
+        m += d[p];
+        if (CX[p] != 0) jx += (double)CX[p] * d[p];
+        if (CY[p] != 0) jy += (double)CY[p] * d[p];
+        if (c2_of(p) != 0) e += (double)c2_of(p) * d[p];
+    }
+    acc[0] += m;
+    acc[1] += R * jx;
+    acc[2] += R * jy;
+    acc[3] += 0.5 * R2 * e;
+}
+
+// Fixed-tree block reduction of 4 doubles (wavefront butterfly, then the 4
+// wavefronts of the block in order); thread 0 writes out[0..3].
+__device__ inline void block_reduce4(double (&acc)[4], double* out)
+{
+    __shared__ double red[BLOCK / 64][4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+#pragma unroll
+        for (int off = 32; off >= 1; off >>= 1) acc[k] += __shfl_xor(acc[k], off, 64);
+    }
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    if (lane == 0) {
+#pragma unroll
+        for (int k = 0; k < 4; ++k) red[wave][k] = acc[k];
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            double s = red[0][k];
+            for (int w = 1; w < BLOCK / 64; ++w) s += red[w][k];
+            out[k] = s;
+        }
+    }
+}
+
+// ---- kernels ---------------------------------------------------------------
+// Every lattice kernel is launched row-tiled: LX * tpr workgroups of BLOCK
+// lanes (see row_tile_site).
+
+#define D2Q37_SITE(P, L)                                        \
+    using Elem = typename P::T;                                 \
+    constexpr int VL = vl_of<P>();                              \
+    int xrow, r;                                                \
+    int64_t tile;                                               \
+    const bool active = row_tile_site<BLOCK>(g, xrow, r, tile); \
+    Stencil<L, Elem, VL> st;                                    \
+    if (active) st.setup(xrow, r, g)
+
+template <class P, class L>
+__global__ __launch_bounds__(BLOCK) void k_init(typename P::T* __restrict__ dst, Geo g,
+                                                const double* __restrict__ rho,
+                                                const double* __restrict__ ux,
+                                                const double* __restrict__ uy,
+                                                const double* __restrict__ T)
+{
+    D2Q37_SITE(P, L);
+    if (!active) return;
+    const int64_t site = (int64_t)st.x * g.ly + st.y;
+    equilibrium_f64<P::shifted>(rho[site], ux[site], uy[site], T[site],
+                                [&](int p, double v) { store_from_f64<P>(st.own(dst, p, g), p, v); });
+}
+
+// Pure gather, bit copy of every population from its upstream site.
+template <class P, class L>
+__global__ __launch_bounds__(BLOCK) void k_propagate(const typename P::Word* __restrict__ src,
+                                                     typename P::Word* __restrict__ dst, Geo g)
+{
+    using W = typename P::Word;
+    constexpr int VL = vl_of<P>();
+    int xrow, r;
+    int64_t tile;
+    if (!row_tile_site<BLOCK>(g, xrow, r, tile)) return;
+    Stencil<L, W, VL> st;
+    st.setup(xrow, r, g);
+    W w[Q];
+#pragma unroll
+    for (int p = 0; p < Q; ++p) w[p] = ld_stream<W, L::stream_loads>(st.src(src, p, g));
+#pragma unroll
+    for (int p = 0; p < Q; ++p) st_stream(st.own(dst, p, g), w[p]);
+}
+
+// Collide in place on the current buffer.
+template <class P, class L, bool COMP>
+__global__ __launch_bounds__(BLOCK) void k_collide(typename P::T* __restrict__ buf, Geo g, double omega)
+{
+    using C = typename P::C;
+    D2Q37_SITE(P, L);
+    if (!active) return;
+    C v[Q];
+#pragma unroll
+    for (int p = 0; p < Q; ++p) v[p] = P::template load<L::stream_loads>(st.own(buf, p, g), p);
+    collide_site<P, COMP>(v, (C)omega, [&](int p, C res) { P::store(st.own(buf, p, g), p, res); });
+}
+
+// Fused step src -> dst: pull the 37 populations, collide, store at the own
+// site. With AUDIT, the FP64 mass/momentum/energy of the stored result are
+// reduced per workgroup into partials[4 * tile].
+template <class P, class L, bool COMP, bool AUDIT>
+__global__ __launch_bounds__(BLOCK) void k_step(const typename P::T* __restrict__ src,
+                                                typename P::T* __restrict__ dst, Geo g, double omega,
+                                                double* __restrict__ partials)
+{
+    using C = typename P::C;
+    D2Q37_SITE(P, L);
+    double acc[4] = {0.0, 0.0, 0.0, 0.0};
+    if (active) {
+        C v[Q];
+#pragma unroll
+        for (int p = 0; p < Q; ++p) v[p] = P::template load<L::stream_loads>(st.src(src, p, g), p);
+        if constexpr (AUDIT) {
+            double d[Q];
+            collide_site<P, COMP>(v, (C)omega, [&](int p, C res) {
+                P::store(st.own(dst, p, g), p, res);
+                d[p] = stored_as_f64<P>(res, p);
+            });
+            audit_site(d, acc);
+        } else {
+            collide_site<P, COMP>(v, (C)omega, [&](int p, C res) { P::store(st.own(dst, p, g), p, res); });
+        }
+    } else if (!AUDIT) {
+        return;
+    }
+    if constexpr (AUDIT) block_reduce4(acc, partials + 4 * tile);
+}
+
+template <class P, class L>
+__global__ __launch_bounds__(BLOCK) void k_audit(const typename P::T* __restrict__ buf, Geo g,
+                                                 double* __restrict__ partials)
+{
+    D2Q37_SITE(P, L);
+    double acc[4] = {0.0, 0.0, 0.0, 0.0};
+    if (active) {
+        double d[Q];
+#pragma unroll
+        for (int p = 0; p < Q; ++p) d[p] = load_f64<P>(st.own(buf, p, g), p);
+        audit_site(d, acc);
+    }
+    block_reduce4(acc, partials + 4 * tile);
+}
+
+// Deterministic final sum of nparts partials (strided per thread, then the
+// fixed block tree); adds `base` (the per-site constant of shifted storage
+// times the site count).
+__global__ __launch_bounds__(BLOCK) void k_audit_final(const double* __restrict__ partials, int64_t nparts,
+                                                       double4 base, double* __restrict__ out)
+{
+    double acc[4] = {0.0, 0.0, 0.0, 0.0};
+    for (int64_t i = threadIdx.x; i < nparts; i += BLOCK) {
+#pragma unroll
+        for (int k = 0; k < 4; ++k) acc[k] += partials[4 * i + k];
+    }
+    __shared__ double res[4];
+    block_reduce4(acc, res);
+    if (threadIdx.x == 0) {
+        out[0] = base.x + res[0];
+        out[1] = base.y + res[1];
+        out[2] = base.z + res[2];
+        out[3] = base.w + res[3];
+    }
+}
+
+// FP64 macroscopic fields (thermal units) of the stored state.
+template <class P, class L>
+__global__ __launch_bounds__(BLOCK) void k_moments(const typename P::T* __restrict__ buf, Geo g,
+                                                   double* __restrict__ rho, double* __restrict__ ux,
+                                                   double* __restrict__ uy, double* __restrict__ T)
+{
+    D2Q37_SITE(P, L);
+    if (!active) return;
+    double d[Q];
+#pragma unroll
+    for (int p = 0; p < Q; ++p) d[p] = load_f64<P>(st.own(buf, p, g), p);
+    const RawMoments<double> m = raw_moments_plain<double>(d);
+    const Macro<double> s = macro_from_raw<double, P::shifted>(m);
+    const int64_t site = (int64_t)st.x * g.ly + st.y;
+    rho[site] = s.rho;
+    ux[site] = s.Ux / R;
+    uy[site] = s.Uy / R;
+    T[site] = 1.0 + s.t;
+}
+
+// Stored state -> canonical FP64 f[p][x][y].
+template <class P, class L>
+__global__ __launch_bounds__(BLOCK) void k_get(const typename P::T* __restrict__ buf, Geo g,
+                                               double* __restrict__ f)
+{
+    D2Q37_SITE(P, L);
+    if (!active) return;
+    const int64_t site = (int64_t)st.x * g.ly + st.y;
+#pragma unroll
+    for (int p = 0; p < Q; ++p) {
+        const double d = load_f64<P>(st.own(buf, p, g), p);
+        f[(int64_t)p * g.n + site] = P::shifted ? weight(p) + d : d;
+    }
+}
+
+// Canonical FP64 f[p][x][y] -> stored state.
+template <class P, class L>
+__global__ __launch_bounds__(BLOCK) void k_set(typename P::T* __restrict__ buf, Geo g,
+                                               const double* __restrict__ f)
+{
+    D2Q37_SITE(P, L);
+    if (!active) return;
+    const int64_t site = (int64_t)st.x * g.ly + st.y;
+#pragma unroll
+    for (int p = 0; p < Q; ++p) {
+        const double d = f[(int64_t)p * g.n + site];
+        store_from_f64<P>(st.own(buf, p, g), p, P::shifted ? d - weight(p) : d);
+    }
+}
+
+// Streaming copy of 16-byte words (the achievable-bandwidth reference):
+// each thread moves COPY_UNROLL words, all loads issued before the stores.
+constexpr int COPY_UNROLL = 4;
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+__global__ __launch_bounds__(BLOCK) void k_copy16(const u32x4* __restrict__ src, u32x4* __restrict__ dst,
+                                                  int64_t n16)
+{
+    const int64_t base = (int64_t)blockIdx.x * BLOCK * COPY_UNROLL + threadIdx.x;
+    u32x4 v[COPY_UNROLL];
+#pragma unroll
+    for (int k = 0; k < COPY_UNROLL; ++k) {
+        const int64_t i = base + (int64_t)k * BLOCK;
+        if (i < n16) v[k] = ld_stream(src + i);
+    }
+#pragma unroll
+    for (int k = 0; k < COPY_UNROLL; ++k) {
+        const int64_t i = base + (int64_t)k * BLOCK;
+        if (i < n16) st_stream(dst + i, v[k]);
+    }
+}
+
+}  // namespace d2q37

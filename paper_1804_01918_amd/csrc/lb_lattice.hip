@@ -1,0 +1,379 @@
+// C ABI of the D2Q37 lattice (declared in include/lb.h): validation, the
+// host-side context and the kernel launches.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+
+#include "../../include/lb.h"
+#include "lb_kernels.hpp"
+
+using namespace d2q37;
+
+struct lb_ctx {
+    lb_config cfg;
+    Geo geo;
+    hipStream_t stream;
+    int cur;               // buffer holding the current state
+    int64_t steps;         // completed time steps
+    bool half_step;        // a propagate without its collide is pending
+    int64_t nblocks;       // blocks of a full-lattice launch
+    double* partials;      // scratch: 4 doubles per block
+    double* totals;        // scratch: 4 doubles
+    bool fused_audit_valid;
+    char err[512];
+};
+
+namespace {
+
+thread_local char g_err[512];
+
+int fail(lb_ctx* c, int code, const char* fmt, ...)
+{
+    char* dst = c ? c->err : g_err;
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(dst, 512, fmt, ap);
+    va_end(ap);
+    return code;
+}
+
+int check_hip(lb_ctx* c, hipError_t e, const char* what)
+{
+    if (e == hipSuccess) return LB_OK;
+    return fail(c, LB_EDEVICE, "%s: %s", what, hipGetErrorString(e));
+}
+
+int elem_bytes(int precision)
+{
+    switch (precision) {
+        case LB_FP64: return 8;
+        case LB_FP32_SHIFTED: return 4;
+        case LB_FP16_SHIFTED: return 2;
+        default: return 0;
+    }
+}
+
+bool layout_ok(int layout) { return layout >= LB_SOA && layout <= LB_CAOSOA; }
+
+int64_t div_up(int64_t a, int64_t b) { return (a + b - 1) / b; }
+
+size_t round256(size_t b) { return (b + 255) & ~(size_t)255; }
+
+// Calls f(P{}, L{}) for the runtime precision and layout.
+template <class P, class F>
+void with_layout(int layout, F&& f)
+{
+    constexpr int VL = vl_of<P>();
+    switch (layout) {
+        case LB_SOA: f(P{}, Layout<LAYOUT_SOA, VL>{}); break;
+        case LB_AOS: f(P{}, Layout<LAYOUT_AOS, VL>{}); break;
+        case LB_CSOA: f(P{}, Layout<LAYOUT_CSOA, VL>{}); break;
+        default: f(P{}, Layout<LAYOUT_CAOSOA, VL>{}); break;
+    }
+}
+
+template <class F>
+void with_config(const lb_config& cfg, F&& f)
+{
+    switch (cfg.precision) {
+        case LB_FP64: with_layout<PrecF64>(cfg.layout, f); break;
+        case LB_FP32_SHIFTED: with_layout<PrecF32S>(cfg.layout, f); break;
+        default: with_layout<PrecF16S>(cfg.layout, f); break;
+    }
+}
+
+bool aligned256(const void* p) { return ((uintptr_t)p & 255u) == 0; }
+
+void* cur_buf(lb_ctx* c) { return c->cfg.buf[c->cur]; }
+void* other_buf(lb_ctx* c) { return c->cfg.buf[c->cur ^ 1]; }
+
+int launch_status(lb_ctx* c, const char* what) { return check_hip(c, hipGetLastError(), what); }
+
+dim3 grid_of(const lb_ctx* c) { return dim3((unsigned)c->nblocks); }
+
+}  // namespace
+
+extern "C" {
+
+size_t lb_buffer_bytes(int32_t lx, int32_t ly, int32_t precision, int32_t layout)
+{
+    const int eb = elem_bytes(precision);
+    if (lx < 1 || ly < 1 || eb == 0 || !layout_ok(layout)) return 0;
+    const int64_t n = (int64_t)lx * ly;
+    if (n >= ((int64_t)1 << 31)) return 0;
+    if (layout == LB_CSOA || layout == LB_CAOSOA) {
+        const int vl = 128 / eb;
+        if (ly % vl != 0) return 0;
+    }
+    return round256((size_t)n * Q * eb);
+}
+
+size_t lb_scratch_bytes(int32_t lx, int32_t ly)
+{
+    if (lx < 1 || ly < 1) return 0;
+    const int64_t n = (int64_t)lx * ly;
+    if (n >= ((int64_t)1 << 31)) return 0;
+    // one partial sum of 4 doubles per row-tiled workgroup, plus the totals
+    return round256((size_t)((int64_t)lx * div_up(ly, BLOCK) * 4 + 4) * sizeof(double));
+}
+
+int lb_init(lb_ctx** out, const lb_config* cfg, const double* rho, const double* ux, const double* uy,
+            const double* T)
+{
+    if (!out) return fail(nullptr, LB_EINVAL, "lb_init: out is NULL");
+    *out = nullptr;
+    if (!cfg) return fail(nullptr, LB_EINVAL, "lb_init: cfg is NULL");
+    const lb_config& k = *cfg;
+    if (k.lx < 1 || k.ly < 1) return fail(nullptr, LB_EINVAL, "lb_init: extents %d x %d must be >= 1", k.lx, k.ly);
+    if ((int64_t)k.lx * k.ly >= ((int64_t)1 << 31))
+        return fail(nullptr, LB_EINVAL, "lb_init: %d x %d sites exceed 2^31 - 1", k.lx, k.ly);
+    if (!(k.tau > 0.5) || !std::isfinite(k.tau))
+        return fail(nullptr, LB_EINVAL, "lb_init: tau = %g must be finite and > 0.5", k.tau);
+    if (elem_bytes(k.precision) == 0) return fail(nullptr, LB_EUNSUPPORTED, "lb_init: unknown precision %d", k.precision);
+    if (!layout_ok(k.layout)) return fail(nullptr, LB_EUNSUPPORTED, "lb_init: unknown layout %d", k.layout);
+    const size_t bb = lb_buffer_bytes(k.lx, k.ly, k.precision, k.layout);
+    if (bb == 0)
+        return fail(nullptr, LB_EUNSUPPORTED, "lb_init: layout %d needs LY (%d) to be a multiple of %d", k.layout,
+                    k.ly, 128 / elem_bytes(k.precision));
+    for (int i = 0; i < 2; ++i)
+        if (!k.buf[i] || !aligned256(k.buf[i]))
+            return fail(nullptr, LB_EINVAL, "lb_init: buf[%d] is NULL or not 256-byte aligned", i);
+    if (k.buf[0] == k.buf[1]) return fail(nullptr, LB_EINVAL, "lb_init: buf[0] and buf[1] must differ");
+    if (!k.scratch || !aligned256(k.scratch)) return fail(nullptr, LB_EINVAL, "lb_init: scratch is NULL or misaligned");
+    if (k.scratch_bytes < lb_scratch_bytes(k.lx, k.ly))
+        return fail(nullptr, LB_EINVAL, "lb_init: scratch_bytes %zu < %zu", k.scratch_bytes,
+                    lb_scratch_bytes(k.lx, k.ly));
+    if (!rho || !ux || !uy || !T) return fail(nullptr, LB_EINVAL, "lb_init: a field pointer is NULL");
+
+    lb_ctx* c = new (std::nothrow) lb_ctx();
+    if (!c) return fail(nullptr, LB_EINVAL, "lb_init: out of host memory");
+    c->cfg = k;
+    c->geo.lx = k.lx;
+    c->geo.ly = k.ly;
+    c->geo.n = (int64_t)k.lx * k.ly;
+    c->geo.lyv = (k.layout == LB_CSOA || k.layout == LB_CAOSOA) ? k.ly / (128 / elem_bytes(k.precision)) : k.ly;
+    c->stream = (hipStream_t)k.stream;
+    c->cur = 0;
+    c->steps = 0;
+    c->half_step = false;
+    c->geo.tpr = (int)div_up(k.ly, BLOCK);
+    c->nblocks = (int64_t)k.lx * c->geo.tpr;
+    c->partials = (double*)k.scratch;
+    c->totals = c->partials + 4 * c->nblocks;
+    c->fused_audit_valid = false;
+    c->err[0] = 0;
+
+    with_config(k, [&](auto p, auto l) {
+        using P = decltype(p);
+        using L = decltype(l);
+        hipLaunchKernelGGL((k_init<P, L>), grid_of(c), dim3(BLOCK), 0, c->stream, (typename P::T*)k.buf[0],
+                           c->geo, rho, ux, uy, T);
+    });
+    const int rc = launch_status(c, "lb_init: launch");
+    if (rc != LB_OK) {
+        snprintf(g_err, sizeof g_err, "%s", c->err);
+        delete c;
+        return rc;
+    }
+    *out = c;
+    return LB_OK;
+}
+
+int lb_propagate(lb_ctx* c)
+{
+    if (!c) return fail(nullptr, LB_EINVAL, "lb_propagate: ctx is NULL");
+    with_config(c->cfg, [&](auto p, auto l) {
+        using P = decltype(p);
+        using L = decltype(l);
+        hipLaunchKernelGGL((k_propagate<P, L>), grid_of(c), dim3(BLOCK), 0, c->stream,
+                           (const typename P::Word*)cur_buf(c), (typename P::Word*)other_buf(c), c->geo);
+    });
+    const int rc = launch_status(c, "lb_propagate");
+    if (rc != LB_OK) return rc;
+    c->cur ^= 1;
+    c->half_step = true;
+    c->fused_audit_valid = false;
+    return LB_OK;
+}
+
+int lb_collide(lb_ctx* c)
+{
+    if (!c) return fail(nullptr, LB_EINVAL, "lb_collide: ctx is NULL");
+    const double omega = 1.0 / c->cfg.tau;
+    const bool comp = c->cfg.compensated != 0;
+    with_config(c->cfg, [&](auto p, auto l) {
+        using P = decltype(p);
+        using L = decltype(l);
+        if (comp)
+            hipLaunchKernelGGL((k_collide<P, L, true>), grid_of(c), dim3(BLOCK), 0, c->stream,
+                               (typename P::T*)cur_buf(c), c->geo, omega);
+        else
+            hipLaunchKernelGGL((k_collide<P, L, false>), grid_of(c), dim3(BLOCK), 0, c->stream,
+                               (typename P::T*)cur_buf(c), c->geo, omega);
+    });
+    const int rc = launch_status(c, "lb_collide");
+    if (rc != LB_OK) return rc;
+    if (c->half_step) {
+        c->steps += 1;
+        c->half_step = false;
+    }
+    c->fused_audit_valid = false;
+    return LB_OK;
+}
+
+int lb_step(lb_ctx* c, int32_t nsteps)
+{
+    if (!c) return fail(nullptr, LB_EINVAL, "lb_step: ctx is NULL");
+    if (nsteps < 0) return fail(c, LB_EINVAL, "lb_step: nsteps = %d < 0", nsteps);
+    if (nsteps == 0) return LB_OK;
+    const double omega = 1.0 / c->cfg.tau;
+    const bool comp = c->cfg.compensated != 0;
+    for (int32_t s = 0; s < nsteps; ++s) {
+        const bool audit = c->cfg.audit && s == nsteps - 1;
+        with_config(c->cfg, [&](auto p, auto l) {
+            using P = decltype(p);
+            using L = decltype(l);
+            const auto* src = (const typename P::T*)cur_buf(c);
+            auto* dst = (typename P::T*)other_buf(c);
+#define D2Q37_STEP(CMP, AUD)                                                                              \
+    hipLaunchKernelGGL((k_step<P, L, CMP, AUD>), grid_of(c), dim3(BLOCK), 0, c->stream, src, dst, c->geo, omega, \
+                       c->partials)
+            if (comp) {
+                if (audit) D2Q37_STEP(true, true); else D2Q37_STEP(true, false);
+            } else {
+                if (audit) D2Q37_STEP(false, true); else D2Q37_STEP(false, false);
+            }
+#undef D2Q37_STEP
+        });
+        const int rc = launch_status(c, "lb_step");
+        if (rc != LB_OK) return rc;
+        c->cur ^= 1;
+        c->steps += 1;
+        c->fused_audit_valid = audit;
+    }
+    return LB_OK;
+}
+
+int lb_moments(lb_ctx* c, double* rho, double* ux, double* uy, double* T)
+{
+    if (!c) return fail(nullptr, LB_EINVAL, "lb_moments: ctx is NULL");
+    if (!rho || !ux || !uy || !T) return fail(c, LB_EINVAL, "lb_moments: a field pointer is NULL");
+    with_config(c->cfg, [&](auto p, auto l) {
+        using P = decltype(p);
+        using L = decltype(l);
+        hipLaunchKernelGGL((k_moments<P, L>), grid_of(c), dim3(BLOCK), 0, c->stream,
+                           (const typename P::T*)cur_buf(c), c->geo, rho, ux, uy, T);
+    });
+    return launch_status(c, "lb_moments");
+}
+
+int lb_get_populations(lb_ctx* c, double* f)
+{
+    if (!c) return fail(nullptr, LB_EINVAL, "lb_get_populations: ctx is NULL");
+    if (!f) return fail(c, LB_EINVAL, "lb_get_populations: f is NULL");
+    with_config(c->cfg, [&](auto p, auto l) {
+        using P = decltype(p);
+        using L = decltype(l);
+        hipLaunchKernelGGL((k_get<P, L>), grid_of(c), dim3(BLOCK), 0, c->stream, (const typename P::T*)cur_buf(c),
+                           c->geo, f);
+    });
+    return launch_status(c, "lb_get_populations");
+}
+
+int lb_set_populations(lb_ctx* c, const double* f)
+{
+    if (!c) return fail(nullptr, LB_EINVAL, "lb_set_populations: ctx is NULL");
+    if (!f) return fail(c, LB_EINVAL, "lb_set_populations: f is NULL");
+    with_config(c->cfg, [&](auto p, auto l) {
+        using P = decltype(p);
+        using L = decltype(l);
+        hipLaunchKernelGGL((k_set<P, L>), grid_of(c), dim3(BLOCK), 0, c->stream, (typename P::T*)cur_buf(c), c->geo,
+                           f);
+    });
+    c->fused_audit_valid = false;
+    return launch_status(c, "lb_set_populations");
+}
+
+int lb_audit(lb_ctx* c, double out[4])
+{
+    if (!c) return fail(nullptr, LB_EINVAL, "lb_audit: ctx is NULL");
+    if (!out) return fail(c, LB_EINVAL, "lb_audit: out is NULL");
+    if (!c->fused_audit_valid) {
+        with_config(c->cfg, [&](auto p, auto l) {
+            using P = decltype(p);
+            using L = decltype(l);
+            hipLaunchKernelGGL((k_audit<P, L>), grid_of(c), dim3(BLOCK), 0, c->stream,
+                               (const typename P::T*)cur_buf(c), c->geo, c->partials);
+        });
+        const int rc = launch_status(c, "lb_audit: partials");
+        if (rc != LB_OK) return rc;
+    }
+    const double n = (double)c->geo.n;
+    const bool shifted = c->cfg.precision != LB_FP64;
+    const double4 base = shifted ? double4{n, 0.0, 0.0, n} : double4{0.0, 0.0, 0.0, 0.0};
+    hipLaunchKernelGGL(k_audit_final, dim3(1), dim3(BLOCK), 0, c->stream, (const double*)c->partials,
+                       (int64_t)c->nblocks, base, c->totals);
+    int rc = launch_status(c, "lb_audit: final");
+    if (rc != LB_OK) return rc;
+    rc = check_hip(c, hipMemcpyAsync(out, c->totals, 4 * sizeof(double), hipMemcpyDeviceToHost, c->stream),
+                   "lb_audit: copy");
+    if (rc != LB_OK) return rc;
+    rc = check_hip(c, hipStreamSynchronize(c->stream), "lb_audit: synchronize");
+    if (rc != LB_OK) return rc;
+    for (int i = 0; i < 4; ++i)
+        if (!std::isfinite(out[i])) return fail(c, LB_ENONFINITE, "lb_audit: total %d is not finite", i);
+    return LB_OK;
+}
+
+int lb_current_buffer(const lb_ctx* c) { return c ? c->cur : -1; }
+
+int64_t lb_steps_done(const lb_ctx* c) { return c ? c->steps : -1; }
+
+void lb_destroy(lb_ctx* c) { delete c; }
+
+const char* lb_strerror(int code)
+{
+    switch (code) {
+        case LB_OK: return "success";
+        case LB_EINVAL: return "invalid argument";
+        case LB_EDEVICE: return "HIP device error";
+        case LB_EUNSUPPORTED: return "unsupported combination";
+        case LB_ENONFINITE: return "non-finite lattice totals";
+        default: return "unknown error code";
+    }
+}
+
+const char* lb_last_error(const lb_ctx* c) { return c ? c->err : g_err; }
+
+int lb_model_constants(double* r, double* w, int32_t* cvec)
+{
+    if (r) *r = R;
+    for (int p = 0; p < Q; ++p) {
+        if (w) w[p] = weight(p);
+        if (cvec) {
+            cvec[2 * p] = CX[p];
+            cvec[2 * p + 1] = CY[p];
+        }
+    }
+    return LB_OK;
+}
+
+int lb_copy(void* dst, const void* src, size_t bytes, void* stream)
+{
+    if (!dst || !src || (bytes & 15u) || ((uintptr_t)dst & 15u) || ((uintptr_t)src & 15u))
+        return fail(nullptr, LB_EINVAL, "lb_copy: NULL or misaligned pointer, or size not a multiple of 16");
+    if (bytes == 0) return LB_OK;
+    const int64_t n16 = (int64_t)(bytes / 16);
+    const int64_t blocks = div_up(n16, (int64_t)BLOCK * COPY_UNROLL);
+    if (blocks > 0x7fffffff) return fail(nullptr, LB_EINVAL, "lb_copy: %zu bytes is too large", bytes);
+    hipLaunchKernelGGL(k_copy16, dim3((unsigned)blocks), dim3(BLOCK), 0, (hipStream_t)stream, (const u32x4*)src,
+                       (u32x4*)dst, n16);
+    return check_hip(nullptr, hipGetLastError(), "lb_copy");
+}
+
+}  // extern "C"

@@ -1,0 +1,255 @@
+"""Thin ctypes binding of libd2q37 (C ABI in include/lb.h).
+
+Argument marshalling only: every step of the lattice update runs in the HIP
+kernels of the library. PyTorch provides the device memory (the two
+population buffers and the scratch area) and the stream. There is no CPU
+fallback: if the library or a GPU is missing, calls raise.
+"""
+from __future__ import annotations
+
+import ctypes
+import functools
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+# D2Q37_LIB selects another build of the same library (e.g. one compiled
+# with different -D options); the default is the in-tree build.
+LIB_PATH = os.environ.get("D2Q37_LIB") or os.path.join(HERE, "libd2q37.so")
+
+LB_OK, LB_EINVAL, LB_EDEVICE, LB_EUNSUPPORTED, LB_ENONFINITE = 0, -1, -2, -3, -4
+PRECISIONS = {"f64": 0, "f32s": 1, "f16s": 2}
+LAYOUTS = {"soa": 0, "aos": 1, "csoa": 2, "caosoa": 3}
+ELEM_BYTES = {"f64": 8, "f32s": 4, "f16s": 2}
+Q = 37
+
+
+class LBError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"{msg} (code {code})")
+        self.code = code
+
+
+class LBNonFinite(LBError):
+    def __init__(self, code: int, msg: str, totals):
+        super().__init__(code, msg)
+        self.totals = totals
+
+
+class Config(ctypes.Structure):
+    _fields_ = [
+        ("lx", ctypes.c_int32),
+        ("ly", ctypes.c_int32),
+        ("tau", ctypes.c_double),
+        ("precision", ctypes.c_int32),
+        ("layout", ctypes.c_int32),
+        ("compensated", ctypes.c_int32),
+        ("audit", ctypes.c_int32),
+        ("buf", ctypes.c_void_p * 2),
+        ("scratch", ctypes.c_void_p),
+        ("scratch_bytes", ctypes.c_size_t),
+        ("stream", ctypes.c_void_p),
+    ]
+
+
+_VP, _I32, _I64, _SZ, _D = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_size_t, ctypes.c_double
+
+_SIGNATURES = {
+    "lb_buffer_bytes": (_SZ, [_I32, _I32, _I32, _I32]),
+    "lb_scratch_bytes": (_SZ, [_I32, _I32]),
+    "lb_init": (ctypes.c_int, [ctypes.POINTER(_VP), ctypes.POINTER(Config), _VP, _VP, _VP, _VP]),
+    "lb_propagate": (ctypes.c_int, [_VP]),
+    "lb_collide": (ctypes.c_int, [_VP]),
+    "lb_step": (ctypes.c_int, [_VP, _I32]),
+    "lb_moments": (ctypes.c_int, [_VP, _VP, _VP, _VP, _VP]),
+    "lb_get_populations": (ctypes.c_int, [_VP, _VP]),
+    "lb_set_populations": (ctypes.c_int, [_VP, _VP]),
+    "lb_audit": (ctypes.c_int, [_VP, ctypes.POINTER(_D)]),
+    "lb_current_buffer": (ctypes.c_int, [_VP]),
+    "lb_steps_done": (_I64, [_VP]),
+    "lb_destroy": (None, [_VP]),
+    "lb_strerror": (ctypes.c_char_p, [ctypes.c_int]),
+    "lb_last_error": (ctypes.c_char_p, [_VP]),
+    "lb_model_constants": (ctypes.c_int, [ctypes.POINTER(_D), ctypes.POINTER(_D), ctypes.POINTER(_I32)]),
+    "lb_copy": (ctypes.c_int, [_VP, _VP, _SZ, _VP]),
+}
+
+
+@functools.lru_cache(maxsize=None)
+def lib() -> ctypes.CDLL:
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(
+            f"{LIB_PATH} is not built; run `python -m paper_1804_01918_amd.build` "
+            "(or __graft_entry__.build()) first")
+    so = ctypes.CDLL(LIB_PATH)
+    for name, (res, args) in _SIGNATURES.items():
+        fn = getattr(so, name)
+        fn.restype = res
+        fn.argtypes = args
+    return so
+
+
+def _check(rc: int, ctx=None, what: str = ""):
+    if rc == LB_OK:
+        return
+    msg = lib().lb_last_error(ctx).decode(errors="replace")
+    raise LBError(rc, f"{what}: {msg}" if what else msg)
+
+
+def buffer_bytes(lx: int, ly: int, precision: str = "f64", layout: str = "soa") -> int:
+    return lib().lb_buffer_bytes(lx, ly, PRECISIONS[precision], LAYOUTS[layout])
+
+
+def scratch_bytes(lx: int, ly: int) -> int:
+    return lib().lb_scratch_bytes(lx, ly)
+
+
+def model_constants():
+    """(r, w[37], c[37, 2]) as compiled into the library."""
+    r = ctypes.c_double()
+    w = np.zeros(Q)
+    c = np.zeros((Q, 2), dtype=np.int32)
+    _check(lib().lb_model_constants(ctypes.byref(r), w.ctypes.data_as(ctypes.POINTER(_D)),
+                                    c.ctypes.data_as(ctypes.POINTER(_I32))))
+    return r.value, w, c
+
+
+def _torch():
+    import torch
+    if not torch.cuda.is_available():
+        raise RuntimeError("libd2q37 needs a ROCm GPU; torch.cuda.is_available() is False")
+    return torch
+
+
+def device_copy(dst, src, stream=None):
+    """Streaming copy kernel of the library (bandwidth reference)."""
+    torch = _torch()
+    s = stream if stream is not None else torch.cuda.current_stream()
+    nbytes = src.numel() * src.element_size()
+    _check(lib().lb_copy(dst.data_ptr(), src.data_ptr(), nbytes, s.cuda_stream), None, "lb_copy")
+
+
+class Lattice:
+    """One D2Q37 lattice on the GPU: two population buffers and scratch owned
+    by PyTorch, kernels from libd2q37, launched on the current stream."""
+
+    def __init__(self, lx: int, ly: int, tau: float, fields, precision: str = "f64",
+                 layout: str = "soa", compensated: bool | None = None, audit: bool = False,
+                 device: str = "cuda"):
+        """compensated=None picks the default of the precision: compensated
+        FP32 moment sums for f32s; plain sums for f16s, whose 11-bit storage
+        rounding is far above the FP32 summation error."""
+        torch = _torch()
+        if compensated is None:
+            compensated = precision == "f32s"
+        self.lx, self.ly, self.tau = int(lx), int(ly), float(tau)
+        self.precision, self.layout = precision, layout
+        self.device = torch.device(device)
+        self.stream = torch.cuda.current_stream(self.device)
+        nbytes = lib().lb_buffer_bytes(self.lx, self.ly, PRECISIONS[precision], LAYOUTS[layout])
+        if nbytes == 0:
+            raise LBError(LB_EUNSUPPORTED if self.lx >= 1 and self.ly >= 1 else LB_EINVAL,
+                          f"invalid lattice {lx}x{ly} for precision={precision} layout={layout}")
+        sbytes = lib().lb_scratch_bytes(self.lx, self.ly)
+        self.bufs = [torch.empty(nbytes, dtype=torch.uint8, device=self.device) for _ in range(2)]
+        self.scratch = torch.empty(sbytes, dtype=torch.uint8, device=self.device)
+        self.cfg = Config()
+        self.cfg.lx, self.cfg.ly, self.cfg.tau = self.lx, self.ly, self.tau
+        self.cfg.precision, self.cfg.layout = PRECISIONS[precision], LAYOUTS[layout]
+        self.cfg.compensated, self.cfg.audit = int(bool(compensated)), int(bool(audit))
+        self.cfg.buf[0], self.cfg.buf[1] = self.bufs[0].data_ptr(), self.bufs[1].data_ptr()
+        self.cfg.scratch, self.cfg.scratch_bytes = self.scratch.data_ptr(), sbytes
+        self.cfg.stream = self.stream.cuda_stream
+        fl = [self._field(a) for a in fields]
+        self._ctx = ctypes.c_void_p()
+        _check(lib().lb_init(ctypes.byref(self._ctx), ctypes.byref(self.cfg),
+                             *[a.data_ptr() for a in fl]), None, "lb_init")
+        self._fields_keepalive = fl
+
+    def _field(self, a):
+        torch = _torch()
+        if isinstance(a, np.ndarray):
+            a = torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64))
+        t = a.to(device=self.device, dtype=torch.float64).contiguous()
+        if tuple(t.shape) != (self.lx, self.ly):
+            raise ValueError(f"field shape {tuple(t.shape)} != {(self.lx, self.ly)}")
+        return t
+
+    @property
+    def ctx(self):
+        if self._ctx is None or not self._ctx.value:
+            raise RuntimeError("lattice is closed")
+        return self._ctx
+
+    # -- the method ---------------------------------------------------------
+    def propagate(self):
+        _check(lib().lb_propagate(self.ctx), self.ctx, "lb_propagate")
+
+    def collide(self):
+        _check(lib().lb_collide(self.ctx), self.ctx, "lb_collide")
+
+    def step(self, nsteps: int = 1):
+        _check(lib().lb_step(self.ctx, int(nsteps)), self.ctx, "lb_step")
+
+    # -- readouts -----------------------------------------------------------
+    def moments(self):
+        torch = _torch()
+        out = [torch.empty((self.lx, self.ly), dtype=torch.float64, device=self.device) for _ in range(4)]
+        _check(lib().lb_moments(self.ctx, *[o.data_ptr() for o in out]), self.ctx, "lb_moments")
+        return tuple(out)
+
+    def get_populations(self):
+        torch = _torch()
+        f = torch.empty((Q, self.lx, self.ly), dtype=torch.float64, device=self.device)
+        _check(lib().lb_get_populations(self.ctx, f.data_ptr()), self.ctx, "lb_get_populations")
+        return f
+
+    def set_populations(self, f):
+        torch = _torch()
+        if isinstance(f, np.ndarray):
+            f = torch.from_numpy(np.ascontiguousarray(f, dtype=np.float64))
+        t = f.to(device=self.device, dtype=torch.float64).contiguous()
+        if tuple(t.shape) != (Q, self.lx, self.ly):
+            raise ValueError(f"populations shape {tuple(t.shape)} != {(Q, self.lx, self.ly)}")
+        _check(lib().lb_set_populations(self.ctx, t.data_ptr()), self.ctx, "lb_set_populations")
+        self.stream.synchronize()
+
+    def audit(self) -> np.ndarray:
+        out = (ctypes.c_double * 4)()
+        rc = lib().lb_audit(self.ctx, out)
+        vals = np.array(list(out))
+        if rc == LB_ENONFINITE:
+            raise LBNonFinite(rc, lib().lb_last_error(self.ctx).decode(), vals)
+        _check(rc, self.ctx, "lb_audit")
+        return vals
+
+    def current_buffer(self) -> int:
+        return lib().lb_current_buffer(self.ctx)
+
+    def steps_done(self) -> int:
+        return lib().lb_steps_done(self.ctx)
+
+    def raw_state(self):
+        """Raw bytes of the current buffer (bit-exact checkpoint)."""
+        return self.bufs[self.current_buffer()].clone()
+
+    def load_raw_state(self, raw):
+        self.bufs[self.current_buffer()].copy_(raw)
+
+    def close(self):
+        if self._ctx is not None and self._ctx.value:
+            lib().lb_destroy(self._ctx)
+        self._ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()

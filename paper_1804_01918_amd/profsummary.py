@@ -1,0 +1,142 @@
+"""Summarise rocprofv3 results (rocpd SQLite files) for one kernel.
+
+Inputs: a --kernel-trace --stats run, a --pmc FETCH_SIZE run and a --pmc
+WRITE_SIZE run of the same workload, plus the same two counters taken on the
+library's copy kernel moving a known number of bytes (the calibration: HBM
+bytes per counter unit). Output: a short Markdown summary and an entry in a
+JSON file of per-launch HBM traffic keyed by kernel, tagged with a digest of
+the kernel sources it was measured on.
+
+    python -m paper_1804_01918_amd.profsummary --name k_step_f64_caosoa \\
+        --match "k_step<d2q37::PrecF64, d2q37::Layout<3, 16>, true, false>" \\
+        --trace T.db --fetch F.db --write W.db --copy-fetch CF.db --copy-write CW.db \\
+        --copy-bytes 1241513984 --sites 4194304 --alg-bytes 2483027968 \\
+        --cmd "..." --md profiles/x.md --json profiles/traffic.json
+"""
+from __future__ import annotations
+
+import argparse
+import glob
+import hashlib
+import json
+import os
+import sqlite3
+import statistics
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def source_digest() -> str:
+    h = hashlib.sha256()
+    for path in sorted(glob.glob(os.path.join(ROOT, "paper_1804_01918_amd", "csrc", "*"))):
+        with open(path, "rb") as fh:
+            h.update(os.path.basename(path).encode())
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def _db(path: str) -> sqlite3.Connection:
+    if os.path.isdir(path):
+        cands = sorted(glob.glob(os.path.join(path, "**", "*.db"), recursive=True))
+        if not cands:
+            raise FileNotFoundError(f"no .db under {path}")
+        path = cands[0]
+    return sqlite3.connect(path)
+
+
+def kernel_durations(trace: str) -> dict[str, list[float]]:
+    """Kernel name -> list of durations in microseconds."""
+    con = _db(trace)
+    out: dict[str, list[float]] = {}
+    for name, start, end in con.execute("select name, start, end from kernels"):
+        out.setdefault(name, []).append((end - start) / 1e3)
+    return out
+
+
+def counter_per_dispatch(db: str, counter: str) -> dict[str, list[float]]:
+    con = _db(db)
+    out: dict[str, list[float]] = {}
+    for name, value in con.execute(
+            "select kernel_name, value from counters_collection where counter_name = ?", (counter,)):
+        out.setdefault(name, []).append(float(value))
+    return out
+
+
+def _pick(d: dict, match: str):
+    hits = [k for k in d if match in k]
+    if not hits:
+        raise KeyError(f"no kernel matches {match!r}; have {list(d)[:8]}")
+    return hits[0], d[hits[0]]
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--name", required=True)
+    ap.add_argument("--match", required=True)
+    ap.add_argument("--trace", required=True)
+    ap.add_argument("--fetch")
+    ap.add_argument("--write")
+    ap.add_argument("--copy-fetch")
+    ap.add_argument("--copy-write")
+    ap.add_argument("--copy-match", default="k_copy16")
+    ap.add_argument("--copy-bytes", type=int, default=0)
+    ap.add_argument("--sites", type=int, required=True)
+    ap.add_argument("--alg-bytes", type=int, required=True)
+    ap.add_argument("--cmd", required=True, help="the commands that produced the inputs")
+    ap.add_argument("--md", required=True)
+    ap.add_argument("--json", required=True)
+    a = ap.parse_args()
+
+    durs = kernel_durations(a.trace)
+    kname, kd = _pick(durs, a.match)
+    avg_us = statistics.fmean(kd)
+    lines = [f"# {a.name}: rocprofv3 summary", "", "Commands:", "", "```", a.cmd.strip(), "```", "",
+             "## Kernel trace (--kernel-trace --stats)", "",
+             "| kernel | calls | avg us | min us | max us |", "|---|---|---|---|---|"]
+    for name, v in sorted(durs.items(), key=lambda kv: -sum(kv[1])):
+        lines.append(f"| `{name[:110]}` | {len(v)} | {statistics.fmean(v):.2f} | {min(v):.2f} | {max(v):.2f} |")
+    lines += ["", f"Dominant kernel `{kname}`: average {avg_us:.2f} us per launch; "
+              f"algorithmic bytes per launch {a.alg_bytes} -> {a.alg_bytes / (avg_us * 1e-6) / 1e9:.0f} GB/s.", ""]
+
+    entry = {"kernel": kname, "sites": a.sites, "avg_launch_us": avg_us,
+             "algorithmic_bytes_per_launch": a.alg_bytes}
+    if a.fetch and a.write and a.copy_fetch and a.copy_write and a.copy_bytes:
+        _, fk = _pick(counter_per_dispatch(a.fetch, "FETCH_SIZE"), a.match)
+        _, wk = _pick(counter_per_dispatch(a.write, "WRITE_SIZE"), a.match)
+        _, cf = _pick(counter_per_dispatch(a.copy_fetch, "FETCH_SIZE"), a.copy_match)
+        _, cw = _pick(counter_per_dispatch(a.copy_write, "WRITE_SIZE"), a.copy_match)
+        fk_m, wk_m = statistics.median(fk), statistics.median(wk)
+        cf_m, cw_m = statistics.median(cf), statistics.median(cw)
+        sf = a.copy_bytes / (cf_m * 1024.0)
+        sw = a.copy_bytes / (cw_m * 1024.0)
+        read_b, write_b = fk_m * 1024.0 * sf, wk_m * 1024.0 * sw
+        entry.update({"fetch_kib_per_dispatch": fk_m, "write_kib_per_dispatch": wk_m,
+                      "copy_fetch_kib": cf_m, "copy_write_kib": cw_m, "copy_bytes": a.copy_bytes,
+                      "fetch_scale": sf, "write_scale": sw, "hbm_read_bytes": read_b,
+                      "hbm_write_bytes": write_b, "hbm_bytes_per_launch": read_b + write_b})
+        lines += ["## HBM traffic (--pmc FETCH_SIZE, --pmc WRITE_SIZE; medians per dispatch)", "",
+                  "| quantity | value |", "|---|---|",
+                  f"| FETCH_SIZE, kernel | {fk_m:.0f} KiB |", f"| WRITE_SIZE, kernel | {wk_m:.0f} KiB |",
+                  f"| FETCH_SIZE, copy of {a.copy_bytes} B | {cf_m:.0f} KiB (scale {sf:.4f}) |",
+                  f"| WRITE_SIZE, copy of {a.copy_bytes} B | {cw_m:.0f} KiB (scale {sw:.4f}) |",
+                  f"| HBM read per launch (scaled) | {read_b:.4g} B |",
+                  f"| HBM write per launch (scaled) | {write_b:.4g} B |",
+                  f"| HBM total / algorithmic | {(read_b + write_b) / a.alg_bytes:.4f} |", ""]
+    lines += [f"Kernel sources digest: `{source_digest()}`", ""]
+    with open(a.md, "w") as fh:
+        fh.write("\n".join(lines))
+
+    rec = {"source_digest": source_digest(), "kernels": {}}
+    if os.path.exists(a.json):
+        with open(a.json) as fh:
+            old = json.load(fh)
+        if old.get("source_digest") == rec["source_digest"]:
+            rec = old
+    rec["kernels"][a.name] = entry
+    with open(a.json, "w") as fh:
+        json.dump(rec, fh, indent=1, sort_keys=True)
+    print(json.dumps(entry))
+
+
+if __name__ == "__main__":
+    main()
