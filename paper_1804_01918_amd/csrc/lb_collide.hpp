@@ -29,6 +29,20 @@ namespace d2q37 {
 __device__ inline double fma_(double a, double b, double c) { return __builtin_fma(a, b, c); }
 __device__ inline float fma_(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
 
+// Product with a model constant k. In FP32 the constant is carried as a
+// pair hi + lo (hi = k rounded to FP32, lo = the FP32 rounding of the rest),
+// so the product is as accurate as with a ~48-bit constant. A single rounded
+// constant would bias the moments of the equilibrium by ~3e-8 relative (for
+// example its momentum by rho u (1 + delta)), and that bias accumulates
+// coherently over the steps.
+__device__ inline double mulk(double a, double k) { return a * k; }
+__device__ inline float mulk(float a, double k)
+{
+    const float hi = (float)k;
+    const float lo = (float)(k - (double)hi);
+    return __builtin_fmaf(a, hi, a * lo);
+}
+
 // ---- compensated FP32 summation ------------------------------------------
 // Knuth's TwoSum: a + b = s + e exactly, for any ordering of |a|, |b|.
 __device__ inline void two_sum(float a, float b, float& s, float& e)
@@ -125,13 +139,13 @@ __device__ inline Macro<C> macro_from_raw(const RawMoments<C>& m)
         s.rho = m.m0;
     }
     const C inv_rho = C(1) / s.rho;
-    s.Ux = C(R2) * m.jx * inv_rho;
-    s.Uy = C(R2) * m.jy * inv_rho;
-    s.u2 = C(THETA) * (s.Ux * s.Ux + s.Uy * s.Uy);
+    s.Ux = mulk(m.jx, R2) * inv_rho;
+    s.Uy = mulk(m.jy, R2) * inv_rho;
+    s.u2 = mulk(s.Ux * s.Ux + s.Uy * s.Uy, THETA);
     if constexpr (SHIFTED)
-        s.t = (C(R2) * m.e - C(2) * m.m0 - s.rho * s.u2) * (C(0.5) * inv_rho);
+        s.t = (mulk(m.e, R2) - C(2) * m.m0 - s.rho * s.u2) * (C(0.5) * inv_rho);
     else
-        s.t = C(0.5) * (C(R2) * m.e * inv_rho - s.u2) - C(1);
+        s.t = C(0.5) * (mulk(m.e, R2) * inv_rho - s.u2) - C(1);
     return s;
 }
 
@@ -149,13 +163,13 @@ __device__ inline void relax_emit(const C (&v)[Q], const Macro<C>& s, C omega, C
     for (int h = 0; h < NSHELL; ++h) {
         const C X2 = C(R2 * SHELL_C2[h]);
         const C q4 = C(R2 * SHELL_C2[h] * (R2 * SHELL_C2[h] - 8.0) + 8.0);  // X2^2 - 8 X2 + 8
-        const C K = kr * C(WSH[h]);
+        const C K = mulk(kr, WSH[h]);
         // A0 - 1
         const C a0m1 = -C(0.5) * u2 + C(0.5) * t * (X2 - C(2))
                        + (C(3) * u2 * u2 + C(6) * t * u2 * (C(4) - X2) + C(3) * t * t * q4) * C(1.0 / 24.0);
         C B0;
         if constexpr (SHIFTED)
-            B0 = omega * C(WSH[h]) * s.drho + K * a0m1;
+            B0 = mulk(omega * s.drho, WSH[h]) + K * a0m1;
         else
             B0 = K * (C(1) + a0m1);
         if (h == 0) {

@@ -145,7 +145,7 @@ __global__ __launch_bounds__(BLOCK) void k_propagate(const typename P::Word* __r
 #pragma unroll
     for (int p = 0; p < Q; ++p) w[p] = ld_stream<W, L::stream_loads>(st.src(src, p, g));
 #pragma unroll
-    for (int p = 0; p < Q; ++p) st_stream(st.own(dst, p, g), w[p]);
+    for (int p = 0; p < Q; ++p) st_stream<W, L::stream_stores>(st.own(dst, p, g), w[p]);
 }
 
 // Collide in place on the current buffer.
@@ -158,7 +158,7 @@ __global__ __launch_bounds__(BLOCK) void k_collide(typename P::T* __restrict__ b
     C v[Q];
 #pragma unroll
     for (int p = 0; p < Q; ++p) v[p] = P::template load<L::stream_loads>(st.own(buf, p, g), p);
-    collide_site<P, COMP>(v, (C)omega, [&](int p, C res) { P::store(st.own(buf, p, g), p, res); });
+    collide_site<P, COMP>(v, (C)omega, [&](int p, C res) { P::template store<L::stream_stores>(st.own(buf, p, g), p, res); });
 }
 
 // Fused step src -> dst: pull the 37 populations, collide, store at the own
@@ -179,12 +179,12 @@ __global__ __launch_bounds__(BLOCK) void k_step(const typename P::T* __restrict_
         if constexpr (AUDIT) {
             double d[Q];
             collide_site<P, COMP>(v, (C)omega, [&](int p, C res) {
-                P::store(st.own(dst, p, g), p, res);
+                P::template store<L::stream_stores>(st.own(dst, p, g), p, res);
                 d[p] = stored_as_f64<P>(res, p);
             });
             audit_site(d, acc);
         } else {
-            collide_site<P, COMP>(v, (C)omega, [&](int p, C res) { P::store(st.own(dst, p, g), p, res); });
+            collide_site<P, COMP>(v, (C)omega, [&](int p, C res) { P::template store<L::stream_stores>(st.own(dst, p, g), p, res); });
         }
     } else if (!AUDIT) {
         return;

@@ -36,11 +36,12 @@ namespace d2q37 {
 #define D2Q37_NT_LOADS 1
 #endif
 
-template <typename T>
+template <typename T, bool NT = true>
 __device__ inline void st_stream(T* a, T v)
 {
 #if D2Q37_NT_STORES
-    __builtin_nontemporal_store(v, a);
+    if constexpr (NT) __builtin_nontemporal_store(v, a);
+    else *a = v;
 #else
     *a = v;
 #endif
@@ -78,7 +79,8 @@ struct PrecF64 {
     static constexpr bool shifted = false;
     template <bool NT = true>
     __device__ static C load(const T* a, int /*p*/) { return ld_stream<T, NT>(a); }
-    __device__ static void store(T* a, int /*p*/, C v) { st_stream(a, v); }
+    template <bool NT = true>
+    __device__ static void store(T* a, int /*p*/, C v) { st_stream<T, NT>(a, v); }
 };
 
 // Shifted deviations g = f - w in FP32.
@@ -90,7 +92,8 @@ struct PrecF32S {
     static constexpr bool shifted = true;
     template <bool NT = true>
     __device__ static C load(const T* a, int /*p*/) { return ld_stream<T, NT>(a); }
-    __device__ static void store(T* a, int /*p*/, C v) { st_stream(a, v); }
+    template <bool NT = true>
+    __device__ static void store(T* a, int /*p*/, C v) { st_stream<T, NT>(a, v); }
 };
 
 // Shifted deviations stored as FP16 of g * s_p (s_p an exact power of two),
@@ -107,9 +110,10 @@ struct PrecF16S {
     {
         return __half2float(__ushort_as_half(ld_stream<T, NT>(a))) * (1.0f / scale(p));
     }
+    template <bool NT = true>
     __device__ static void store(T* a, int p, C v)
     {
-        st_stream(a, (uint16_t)__half_as_ushort(__float2half_rn(v * scale(p))));
+        st_stream<T, NT>(a, (uint16_t)__half_as_ushort(__float2half_rn(v * scale(p))));
     }
 };
 
@@ -129,10 +133,11 @@ template <int LK, int VL>
 struct Layout {
     static constexpr int kind = LK;
     static constexpr bool clustered = (LK == LAYOUT_CSOA || LK == LAYOUT_CAOSOA);
-    // In AoS the 37 loads of a wavefront hit the same lines at a 296-byte
-    // lane stride, so the lines must stay cached between them: no streaming
-    // hint on its loads.
+    // In AoS the 37 loads (stores) of a wavefront touch the same lines at a
+    // 37-element lane stride, so the lines must stay cached between them: no
+    // streaming hint on its accesses.
     static constexpr bool stream_loads = (LK != LAYOUT_AOS);
+    static constexpr bool stream_stores = (LK != LAYOUT_AOS);
 
     // Population term of the address.
     __device__ static int64_t pterm(int p, const Geo& g)

@@ -1,0 +1,124 @@
+"""Parity at the full workload sizes, in the launch configuration the
+benchmark times (2048 x 2048 and 8192 x 8192, CAoSoA layout, fused step).
+
+* Sampled parity: after n steps from the seeded state, sampled sites
+  (random ones plus the corners and edges, where the periodic wrap acts) are
+  compared with the oracle evaluated on each site's dependency window.
+* Properties after 1000 steps: the shear wave decays at the rate kinetic
+  theory gives, exp(-nu k^2 t) with nu = theta T (tau - 1/2), and the FP64
+  lattice totals of mass, momentum and energy are conserved to rounding.
+"""
+import numpy as np
+import pytest
+
+from oracle import lbm
+from paper_1804_01918_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+from paper_1804_01918_amd import lb  # noqa: E402
+
+EPS = {"f64": 2.0 ** -53, "f32s": 2.0 ** -24, "f16s": 2.0 ** -11}
+
+
+def _sample_sites(lx, ly, n, seed):
+    rng = np.random.default_rng(seed)
+    pts = {(0, 0), (lx - 1, ly - 1), (0, ly - 1), (lx - 1, 0), (lx // 2, 0), (0, ly // 2), (1, 2),
+           (lx - 2, ly - 3)}
+    while len(pts) < n:
+        pts.add((int(rng.integers(lx)), int(rng.integers(ly))))
+    return sorted(pts)
+
+
+def _gather(lat, sites):
+    f = lat.get_populations()
+    xs = torch.tensor([s[0] for s in sites], device=f.device)
+    ys = torch.tensor([s[1] for s in sites], device=f.device)
+    out = f[:, xs, ys].T.contiguous().cpu().numpy()
+    del f
+    torch.cuda.empty_cache()
+    return out
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32s", "f16s"])
+@pytest.mark.parametrize("kind", ["shear_wave", "rayleigh_taylor"])
+def test_2048_sampled_parity(consts, prec, kind):
+    L, n, tau = 2048, 3, 0.8
+    fields = inputs.make_state(kind, L, L, seed=0)
+    sites = _sample_sites(L, L, 96, seed=5)
+    with lb.Lattice(L, L, tau, fields, precision=prec, layout="caosoa") as lat:
+        lat.step(n)
+        got = _gather(lat, sites)
+    ref = lbm.run_window(fields, sites, n, tau)
+    w = consts["w"][None, :]
+    err = np.max(np.abs(got - ref) / w)
+    if prec == "f64":
+        assert err < 1e-13
+    else:
+        # n roundings of the stored deviation, each <= eps |g / w|; plus the
+        # initial rounding of the equilibrium
+        A = float(np.max(np.abs(ref - w) / w))
+        assert err <= (n + 1) * EPS[prec] * A * 4, (err, A)
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32s"])
+def test_8192_sampled_parity(consts, prec):
+    """Largest workload size (8192 x 8192, about 20 GB of FP32 populations
+    or 40 GB of FP64), one step from the Rayleigh-Taylor-like state."""
+    L, n, tau = 8192, 1, 0.8
+    fields = inputs.rayleigh_taylor(L, L, seed=0)
+    sites = _sample_sites(L, L, 48, seed=6)
+    with lb.Lattice(L, L, tau, fields, precision=prec, layout="caosoa") as lat:
+        lat.step(n)
+        got = _gather(lat, sites)
+    torch.cuda.empty_cache()
+    ref = lbm.run_window(fields, sites, n, tau)
+    w = consts["w"][None, :]
+    err = np.max(np.abs(got - ref) / w)
+    if prec == "f64":
+        assert err < 1e-13
+    else:
+        A = float(np.max(np.abs(ref - w) / w))
+        assert err <= (n + 1) * EPS[prec] * A * 4, (err, A)
+
+
+@pytest.mark.parametrize("prec,tol", [("f64", 5e-3), ("f32s", 2e-2)])
+def test_2048_shear_decay_closed_form(consts, prec, tol):
+    """1000 fused steps of the benchmark workload: the u_x mode decays as
+    exp(-nu k^2 t). The relative tolerance on the decay exponent covers the
+    O(k^2) lattice correction (about 1e-6 here) and, for FP32, the coherent
+    storage rounding (about 1e-5 of the amplitude against a 2e-3 decay)."""
+    L, n, tau = 2048, 1000, 0.8
+    fields = inputs.shear_wave(L, L, seed=0)
+    y = torch.arange(L, device="cuda", dtype=torch.float64)
+    basis = torch.sin(2 * np.pi * y / L)
+    with lb.Lattice(L, L, tau, fields, precision=prec, layout="caosoa") as lat:
+        a0 = float(2 * (lat.moments()[1].mean(0) * basis).mean())
+        lat.step(n)
+        a1 = float(2 * (lat.moments()[1].mean(0) * basis).mean())
+    k = 2 * np.pi / L
+    nu = consts["theta"] * 1.0 * (tau - 0.5)
+    rate = -np.log(a1 / a0) / n
+    assert abs(rate / (nu * k * k) - 1) < tol, (rate, nu * k * k)
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32s", "f16s"])
+def test_2048_conservation_1000_steps(consts, prec):
+    L, n = 2048, 1000
+    fields = inputs.rayleigh_taylor(L, L, seed=0)
+    with lb.Lattice(L, L, 0.8, fields, precision=prec, layout="caosoa", audit=True) as lat:
+        a0 = lat.audit()
+        lat.step(n)
+        a1 = lat.audit()
+    M = a0[0]
+    if prec == "f64":
+        # each step moves the totals only by FP64 rounding of O(1) per-site sums
+        assert np.all(np.abs(a1 - a0) <= n * 64 * EPS["f64"] * M)
+    else:
+        # stored deviations |g| <= A w per population: rounding moves the
+        # per-site totals by at most eps * A * O(1) per step
+        f0 = lbm.init(*inputs.rayleigh_taylor(64, 64, seed=0))
+        A = float(np.max(np.abs(f0 - consts["w"][:, None, None]) / consts["w"][:, None, None]))
+        xi2 = float(np.max((consts["xi"] ** 2).sum(1)))
+        assert np.all(np.abs(a1 - a0) <= n * EPS[prec] * A * M * xi2), (a1 - a0)

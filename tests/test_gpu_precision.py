@@ -1,0 +1,131 @@
+"""GPU parity of the shifted reduced-precision forms against the FP64 oracle.
+
+Stated tolerance (per field rho, ux, uy, T, max over sites, after n steps):
+
+    |field_gpu - field_oracle| <= n * eps * A
+
+with eps the unit roundoff of the storage format (2^-24 for FP32, 2^-11 for
+FP16) and A = max over sites and populations of |g_p / w_p| in the initial
+state, the scale of the stored deviations. Each step rounds every stored
+deviation once (relative error <= eps); the moments are weighted sums of the
+deviations with weights summing to O(1) in units of w_p, and in the worst
+case (smooth fields, where neighbouring sites round alike) these errors add
+up coherently over the steps. Storage conversions are checked bit for bit.
+"""
+import numpy as np
+import pytest
+
+from oracle import lbm
+from paper_1804_01918_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+from paper_1804_01918_amd import lb  # noqa: E402
+
+EPS = {"f32s": 2.0 ** -24, "f16s": 2.0 ** -11}
+S16 = {0: 4.0, 1: 8.0, 2: 16.0, 4: 64.0, 5: 256.0, 8: 1024.0, 9: 4096.0, 10: 4096.0}
+
+
+def _bits(a):
+    return np.ascontiguousarray(a).view(np.uint64)
+
+
+def _scale_f16(consts):
+    c2 = (consts["c"] ** 2).sum(1)
+    return np.array([S16[int(v)] for v in c2])[:, None, None]
+
+
+def _deviation_scale(f, consts):
+    w = consts["w"][:, None, None]
+    return float(np.max(np.abs(f - w) / w))
+
+
+@pytest.fixture(scope="module")
+def config1():
+    fields = inputs.random_equilibrium(128, 64, seed=0)
+    f0 = lbm.init(*fields)
+    return fields, f0, lbm.moments(lbm.run(f0, 0.8, 100))
+
+
+def test_f32_storage_roundtrip_bitwise(consts):
+    lx, ly = 24, 32
+    f0 = lbm.init(*inputs.random_equilibrium(lx, ly, seed=3, amp=0.05))
+    f0 = f0 + 1e-3 * consts["w"][:, None, None] * inputs.perturbation(f0.shape, 9)
+    w = consts["w"][:, None, None]
+    with lb.Lattice(lx, ly, 0.8, inputs.random_equilibrium(lx, ly), precision="f32s") as lat:
+        lat.set_populations(f0)
+        got = lat.get_populations().cpu().numpy()
+    want = w + (f0 - w).astype(np.float32).astype(np.float64)
+    assert np.array_equal(_bits(got), _bits(want))
+
+
+def test_f16_storage_roundtrip_bitwise(consts):
+    lx, ly = 24, 64
+    f0 = lbm.init(*inputs.random_equilibrium(lx, ly, seed=4, amp=0.05))
+    f0 = f0 + 1e-3 * consts["w"][:, None, None] * inputs.perturbation(f0.shape, 10)
+    w = consts["w"][:, None, None]
+    s = _scale_f16(consts)
+    with lb.Lattice(lx, ly, 0.8, inputs.random_equilibrium(lx, ly), precision="f16s") as lat:
+        lat.set_populations(f0)
+        got = lat.get_populations().cpu().numpy()
+    want = w + ((f0 - w) * s).astype(np.float16).astype(np.float64) / s
+    assert np.array_equal(_bits(got), _bits(want))
+
+
+def test_f16_scales_are_powers_of_two_near_inverse_weight(consts):
+    s = _scale_f16(consts)[:, 0, 0]
+    assert np.all(np.log2(s) == np.round(np.log2(s)))
+    ws = consts["w"] * s
+    assert np.all((ws > 0.7) & (ws < 1.42))
+
+
+@pytest.mark.parametrize("prec", ["f32s", "f16s"])
+@pytest.mark.parametrize("compensated", [True, False])
+@pytest.mark.parametrize("layout", ["soa", "caosoa"])
+def test_config1_shifted_within_stated_error(consts, config1, prec, compensated, layout):
+    fields, f0, ref = config1
+    n = 100
+    with lb.Lattice(128, 64, 0.8, fields, precision=prec, layout=layout, compensated=compensated) as lat:
+        lat.step(n)
+        got = [t.cpu().numpy() for t in lat.moments()]
+    tol = n * EPS[prec] * _deviation_scale(f0, consts)
+    for name, a, b in zip(("rho", "ux", "uy", "T"), got, ref):
+        err = float(np.max(np.abs(a - b)))
+        assert err <= tol, (name, err, tol)
+
+
+@pytest.mark.parametrize("prec", ["f32s", "f16s"])
+@pytest.mark.parametrize("kind", ["shear_wave", "rayleigh_taylor"])
+def test_shifted_states_within_stated_error(consts, prec, kind):
+    lx, ly, n = 64, 128, 60
+    fields = inputs.make_state(kind, lx, ly, seed=1)
+    f0 = lbm.init(*fields)
+    ref = lbm.moments(lbm.run(f0, 0.8, n))
+    with lb.Lattice(lx, ly, 0.8, fields, precision=prec, layout="caosoa") as lat:
+        lat.step(n)
+        got = [t.cpu().numpy() for t in lat.moments()]
+    tol = n * EPS[prec] * _deviation_scale(f0, consts)
+    for name, a, b in zip(("rho", "ux", "uy", "T"), got, ref):
+        err = float(np.max(np.abs(a - b)))
+        assert err <= tol, (name, err, tol)
+
+
+@pytest.mark.parametrize("prec", ["f32s", "f16s"])
+def test_shifted_audit_drift_within_stated_error(consts, prec):
+    """Lattice totals of mass, momentum and energy move only by rounding:
+    per step at most eps times the summed magnitude of the stored deviations
+    (and their xi, xi^2/2 moments) over the lattice."""
+    lx, ly, n = 64, 128, 100
+    fields = inputs.shear_wave(lx, ly, seed=2)
+    f0 = lbm.init(*fields)
+    xi = consts["xi"]
+    g = np.abs(f0 - consts["w"][:, None, None])
+    scale = np.array([g.sum(), (g * np.abs(xi[:, 0])[:, None, None]).sum(),
+                      (g * np.abs(xi[:, 1])[:, None, None]).sum(),
+                      (g * 0.5 * (xi ** 2).sum(1)[:, None, None]).sum()])
+    with lb.Lattice(lx, ly, 0.8, fields, precision=prec, layout="soa") as lat:
+        a0 = lat.audit()
+        lat.step(n)
+        a1 = lat.audit()
+    assert np.all(np.abs(a1 - a0) <= n * EPS[prec] * scale), (a1 - a0, n * EPS[prec] * scale)

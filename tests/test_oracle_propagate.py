@@ -69,3 +69,15 @@ def test_centre_of_mass_moves_with_hops(consts):
     g = lbm.propagate(h)
     assert abs(g.sum() - M) < 1e-12
     assert np.allclose(cen(g) - cen(h), expected, rtol=0, atol=1e-10)
+
+
+@pytest.mark.parametrize("lx,ly,n", [(16, 16, 1), (16, 20, 2), (9, 7, 3)])
+def test_run_window_matches_periodic_run(lx, ly, n):
+    """The dependency-window evaluation equals the full periodic run bit for
+    bit, including sites whose windows wrap around the edges."""
+    fields = inputs.random_equilibrium(lx, ly, seed=6, amp=0.03)
+    full = lbm.run(lbm.init(*fields), 0.8, n)
+    sites = [(0, 0), (lx - 1, ly - 1), (lx // 2, 1), (3, ly - 2), (lx - 2, ly // 2)]
+    got = lbm.run_window(fields, sites, n, 0.8)
+    for k, (x, y) in enumerate(sites):
+        assert np.array_equal(got[k], full[:, x, y])
