@@ -1,0 +1,152 @@
+"""Pins of the learned-collide oracle: the counter-based generator against
+its published known-answer vectors, the pair law, the conserved-moment
+projection, the residual closed forms, the MLP gradient against finite
+differences, BF16 rounding, Adam and a short training run."""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import lbm, surrogate as S
+from oracle.philox import pair_draws, philox4x32_10, uniform_from_u32
+
+# Known-answer vectors of Philox4x32-10 published with the Random123 library
+# (Salmon et al., SC11): counter, key -> output.
+KAT = [
+    ((0, 0, 0, 0), (0, 0), (0x6627E8D5, 0xE169C58D, 0xBC57AC4C, 0x9B00DBD8)),
+    ((0xFFFFFFFF,) * 4, (0xFFFFFFFF,) * 2, (0x408F276D, 0x41C83B0E, 0xA20BC7C6, 0x6D5451FD)),
+    ((0x243F6A88, 0x85A308D3, 0x13198A2E, 0x03707344), (0xA4093822, 0x299F31D0),
+     (0xD16CFE09, 0x94FDCCEB, 0x5001E420, 0x24126EA1)),
+]
+
+
+@pytest.mark.parametrize("ctr,key,want", KAT)
+def test_philox_known_answers(ctr, key, want):
+    got = philox4x32_10(ctr, key)
+    assert tuple(int(v) for v in got) == want
+
+
+def test_uniform_open_interval_and_fp32_exact():
+    u = uniform_from_u32(np.array([0, 1, 511, 512, 0xFFFFFFFF], dtype=np.uint64))
+    assert np.all((u > 0) & (u < 1))
+    assert np.array_equal(u, u.astype(np.float32).astype(np.float64))
+    assert u[0] == 2.0 ** -24 and u[-1] == 1 - 2.0 ** -24
+
+
+def test_pair_law():
+    rho, ux, uy, T, n = pair_draws(np.arange(20000), seed=3)
+    assert rho.min() >= 0.9 and rho.max() <= 1.1 and T.min() >= 0.9 and T.max() <= 1.1
+    r = np.sqrt(ux ** 2 + uy ** 2)
+    assert r.max() <= 0.1
+    # uniform in the disk: P(r < 0.05) = 1/4
+    assert abs((r < 0.05).mean() - 0.25) < 0.015
+    assert abs(n.mean()) < 0.01 and abs(n.var() - 1) < 0.01
+    assert abs(np.mean(n[:, 0] * n[:, 1])) < 0.02
+
+
+def test_pairs_are_bgk_collisions(consts):
+    tau = 0.8
+    pre, post = S.make_pairs(256, seed=1, tau=tau)
+    xi = consts["xi"]
+    for phi in (np.ones(37), xi[:, 0], xi[:, 1], (xi ** 2).sum(1)):
+        assert np.max(np.abs(pre @ phi - post @ phi)) < 1e-14
+    w = consts["w"]
+    rho, ux, uy, T = S.macro(pre)
+    feq = lbm.init(rho[:, None], ux[:, None], uy[:, None], T[:, None])[:, :, 0].T - w
+    assert np.max(np.abs((pre + tau * (post - pre)) - feq) / w) < 1e-13
+    # the perturbation is 1e-3 w N(0,1) around the drawn equilibrium
+    assert 3e-4 < np.std((pre - feq) / w) < 3e-3
+
+
+def test_gram_is_diagonal():
+    G = S.gram()
+    assert np.allclose(G, np.diag([1.0, 1.0, 1.0, 4.0]), rtol=0, atol=1e-14)
+
+
+def test_projection_properties(consts):
+    rng = np.random.default_rng(0)
+    g = rng.standard_normal((50, 37)) * consts["w"]
+    P = S.conserved_part(g)
+    assert np.allclose(S.conserved_part(P), P, atol=1e-16)
+    for phi in S._basis():
+        assert np.allclose(P @ phi, g @ phi, atol=1e-15)
+
+
+def test_surrogate_equilibrium_conserves_for_any_network(consts):
+    theta = S.init_params(11)
+    norm = np.stack([np.zeros(37), np.ones(37), np.zeros(37), np.full(37, 0.3)])
+    pre, _ = S.make_pairs(64, seed=2, tau=0.8)
+    ghat = S.surrogate_equilibrium(pre, theta, norm)
+    for phi in S._basis():
+        assert np.max(np.abs(ghat @ phi - pre @ phi)) < 1e-14
+
+
+def test_residual_of_exact_equilibrium_is_zero(consts):
+    rho, ux, uy, T, _ = pair_draws(np.arange(200), seed=4)
+    w = consts["w"]
+    g = lbm.init(rho[:, None], ux[:, None], uy[:, None], T[:, None])[:, :, 0].T - w
+    r = S.residual(g, rho, ux, uy, T)
+    assert r.max() < 1e-14
+    # and it sees a perturbed stress
+    g2 = g + 1e-3 * w * (consts["xi"][:, 0] * consts["xi"][:, 1])
+    assert np.all(S.residual(g2, rho, ux, uy, T) > 5e-4)
+
+
+def test_gelu_forms_and_derivative():
+    a = np.linspace(-6, 6, 1001)
+    assert np.allclose(S.gelu(a), 0.5 * a * (1 + np.tanh(S.GELU_C * (a + S.GELU_A * a ** 3))), atol=1e-15)
+    h = 1e-6
+    fd = (S.gelu(a + h) - S.gelu(a - h)) / (2 * h)
+    assert np.max(np.abs(fd - S.gelu_grad(a))) < 1e-8
+
+
+def test_bf16_rounding_examples():
+    x = np.array([1.0, 1 + 2 ** -8, 1 + 3 * 2 ** -9, 1 + 2 ** -7, -2.5, 3.0e-3, 65504.0])
+    got = S.bf16(x)
+    want = np.array([1.0, 1.0, 1 + 2 ** -7, 1 + 2 ** -7, -2.5, 0.0030059814453125, 65536.0])
+    assert np.array_equal(got, want)
+
+
+def test_mlp_gradient_matches_finite_differences():
+    rng = np.random.default_rng(5)
+    theta = S.init_params(7) + 0.01 * rng.standard_normal(S.NPARAM)
+    x = rng.standard_normal((6, 37))
+    y = rng.standard_normal((6, 37))
+    _, g = S.loss_and_grad(theta, x, y, emulate=False)
+    idx = rng.choice(S.NPARAM, 60, replace=False)
+    idx = np.concatenate([idx, [0, 4736, 4736 + 127, S.NPARAM - 1, S.NPARAM - 38]])
+    h = 1e-6
+    for i in idx:
+        tp, tm = theta.copy(), theta.copy()
+        tp[i] += h
+        tm[i] -= h
+        fd = (S.loss_and_grad(tp, x, y, False)[0] - S.loss_and_grad(tm, x, y, False)[0]) / (2 * h)
+        assert abs(fd - g[i]) <= 1e-7 * max(1.0, abs(g[i])) + 1e-9, (i, fd, g[i])
+
+
+def test_adam_first_step_and_convergence():
+    theta = np.array([0.0, 10.0])
+    m = v = np.zeros(2)
+    g = 2 * (theta - 3.0)
+    t1, m, v = S.adam_step(theta, m, v, g, 1, 0.1)
+    assert np.allclose(t1 - theta, [0.1, -0.1], atol=1e-7)
+    th = t1
+    for t in range(2, 3000):
+        th, m, v = S.adam_step(th, m, v, 2 * (th - 3.0), t, 0.05)
+    assert np.allclose(th, 3.0, atol=1e-3)
+
+
+def test_epoch_order_is_a_permutation():
+    for n in (1, 7, 64, 1000, 4096):
+        a, c = S.epoch_order(n, 123, 2)
+        assert math.gcd(a, n) == 1
+        idx = (a * np.arange(n) + c) % n
+        assert len(set(idx.tolist())) == n
+
+
+def test_short_training_reduces_loss():
+    tau = 0.8
+    pre, post = S.make_pairs(4096, seed=9, tau=tau)
+    norm = S.fit_normalization(pre, post, tau)
+    theta, losses = S.train(pre, post, tau, S.init_params(1), norm, batch=256, epochs=6, lr0=3e-3, seed=2)
+    assert losses[-1] < 0.1 * losses[0]
