@@ -153,6 +153,105 @@ int lb_model_constants(double *r, double *w, int32_t *c);
  * pointers) on `stream`: the reference for achievable HBM bandwidth. */
 int lb_copy(void *dst, const void *src, size_t bytes, void *stream);
 
+/* ---------------------------------------------------------------------------
+ * Learned collide. The paper's collide (Section 3) computes the equilibrium
+ * from the moments in closed form; this option replaces that equilibrium by
+ * a small network evaluated on the matrix cores:
+ *   - input z = g / w_p (shifted populations of a site), standardised;
+ *   - MLP 37 -> 128 -> 128 -> 37 with GELU (tanh form), BF16 operands and
+ *     FP32 accumulation; its output y (de-standardised) is the part of the
+ *     equilibrium that the conserved moments do not fix: g_hat = P(g) + d -
+ *     P(d) with d = w_p y and P the orthogonal projection (1/w inner
+ *     product) onto w * {1, xi_x, xi_y, xi^2 - 2}, so mass, momentum and
+ *     energy are those of g;
+ *   - a site falls back to the plain collide when the deviation of g_hat's
+ *     stress and heat flux from their equilibrium values of (rho, u, T)
+ *     exceeds a threshold, or when (rho, |u|, T) leaves the training box
+ *     [0.9, 1.1] x [0, 0.1] x [0.9, 1.1].
+ * Training pairs (pre, post) come from the plain FP32 collide of seeded
+ * random equilibria plus 1e-3 w_p N(0, 1) perturbations; the network is
+ * trained with Adam on the target (g_eq - P(pre)) / w_p, g_eq = pre + tau
+ * (post - pre). Pair arrays are device FP32 [n][37] of shifted populations.
+ * Parameters travel as the packed FP32 vector W1[128][37], b1[128],
+ * W2[128][128], b2[128], W3[37][128], b3[37] (26149 values); the
+ * standardisation as FP32 [4][37]: mean z, sd z, mean y, sd y.
+ * ------------------------------------------------------------------------- */
+typedef struct lb_mlp lb_mlp;
+
+/* Number of packed parameters (26149). */
+size_t lb_mlp_param_count(void);
+
+/* Bytes of device workspace for a network trained with batches of at most
+ * max_batch pairs (a positive multiple of 32); 0 if invalid. */
+size_t lb_mlp_workspace_bytes(int32_t max_batch);
+
+/* Create a network in a caller-owned, 256-byte-aligned device workspace,
+ * launching on `stream`. Parameters start at zero, standardisation at the
+ * identity. */
+int lb_mlp_create(lb_mlp **out, void *workspace, size_t bytes, int32_t max_batch, void *stream);
+void lb_mlp_destroy(lb_mlp *m);
+const char *lb_mlp_last_error(const lb_mlp *m);
+
+/* Xavier-uniform weights and zero biases; the weight with packed index i
+ * draws U from Philox4x32-10 counter (i, 0, 0xFFFFFFFF, 0), key (seed mod
+ * 2^32, seed div 2^32): a (2U - 1), a = sqrt(6 / (fan_in + fan_out)), U the
+ * odd multiple of 2^-24 formed from the top 23 bits of the first output word.
+ * Resets the optimiser. */
+int lb_mlp_init(lb_mlp *m, uint64_t seed);
+
+/* Host FP32 packed parameters in/out (set also resets the optimiser). */
+int lb_mlp_set_params(lb_mlp *m, const float *host_params);
+int lb_mlp_get_params(lb_mlp *m, float *host_params);
+
+/* Host FP32 [4][37] standardisation in/out; standard deviations > 0. */
+int lb_mlp_set_normalization(lb_mlp *m, const float *host_norm);
+int lb_mlp_get_normalization(lb_mlp *m, float *host_norm);
+
+/* Mean and (population) standard deviation of z and of the target y over n
+ * device pairs, summed in FP64 in a fixed order; deviations below 1e-12
+ * become 1. */
+int lb_mlp_fit_normalization(lb_mlp *m, const float *pre, const float *post, int64_t n, double tau);
+
+/* Gradient of the mean squared error (over the n pairs and 37 outputs) at
+ * the current parameters, for the first n device pairs (n a multiple of 32,
+ * <= max_batch); host outputs. */
+int lb_mlp_gradient(lb_mlp *m, const float *pre, const float *post, int32_t n, double tau, float *host_grad,
+                    double *host_loss);
+
+/* Minibatch Adam (beta 0.9, 0.999, eps 1e-8) with learning rate
+ * lr * (1 + cos(pi s / S)) / 2 at step s of S = epochs * (n / batch).
+ * Epoch e visits pair (a i + c) mod n at position i, with (a, c) from
+ * Philox4x32-10 counter (e, 0, 0xFFFFFFFE, 0), key as for lb_mlp_init: a =
+ * first word mod n moved up to the next value coprime with n (1 if 0,
+ * wrapping to 1 at n), c = second word mod n; the n mod batch tail of each
+ * epoch is skipped. max_steps > 0 stops early. host_epoch_loss (may be
+ * NULL) receives the mean batch loss of each epoch. */
+int lb_mlp_train(lb_mlp *m, const float *pre, const float *post, int64_t n, double tau, int32_t batch,
+                 int32_t epochs, float lr, uint64_t seed, int64_t max_steps, double *host_epoch_loss);
+
+/* Learned equilibrium g_hat of n device sites pre[n][37] (plain equilibrium
+ * where the verdict is fallback); residual[n] (FP32) and fallback[n] (int32,
+ * 1 = fallback) may be NULL. Device outputs. */
+int lb_mlp_equilibrium(lb_mlp *m, const float *pre, int64_t n, float threshold, float *geq, float *residual,
+                       int32_t *fallback);
+
+/* n training pairs (device FP32 [n][37] each) from `seed`: pair k draws from
+ * Philox4x32-10 key (seed mod 2^32, seed div 2^32), counters (k mod 2^32,
+ * k div 2^32, j, 0), j = 0..10 (44 words w): rho = 0.9 + 0.2 U(w0), u = 0.1
+ * sqrt(U(w1)) (cos, sin)(2 pi U(w2)), T = 0.9 + 0.2 U(w3), Box-Muller normals
+ * n[2q], n[2q+1] from (U(w[4+2q]), U(w[5+2q])); pre = g_eq(rho, u, T) +
+ * 1e-3 w_p n_p, post = the FP32 collide (relaxation time tau) of pre. */
+int lb_pairgen(float *pre, float *post, int64_t n, uint64_t seed, double tau, void *stream);
+
+/* Use the network for the collide of an FP32-shifted lattice (fused step and
+ * lb_collide); NULL returns to the plain collide. The network must outlive
+ * its use. Sites with residual > threshold fall back to the plain collide. */
+int lb_set_surrogate(lb_ctx *ctx, const lb_mlp *m, double threshold);
+
+/* {fallback sites, collided sites} accumulated by the learned collide since
+ * the previous call (host; synchronises and resets). */
+int lb_surrogate_counts(lb_ctx *ctx, int64_t out[2]);
+
 #ifdef __cplusplus
 }
 #endif

@@ -61,7 +61,7 @@ def make_pairs(n: int, seed: int, tau: float, start: int = 0):
     f = lbm.init(rho[:, None], ux[:, None], uy[:, None], T[:, None])[:, :, 0].T  # (n, 37)
     f = f + PERTURBATION * w * nrm
     post = lbm.collide(f.T[:, :, None], tau)[:, :, 0].T
-    return f - w, post - w
+    return np.ascontiguousarray(f - w), np.ascontiguousarray(post - w)
 
 
 # ---- conserved projection and residual ----------------------------------------

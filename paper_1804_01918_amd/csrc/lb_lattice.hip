@@ -11,6 +11,8 @@
 
 #include "../../include/lb.h"
 #include "lb_kernels.hpp"
+#include "lb_learned.hpp"
+#include "lb_mlp_state.hpp"
 
 using namespace d2q37;
 
@@ -24,6 +26,9 @@ struct lb_ctx {
     int64_t nblocks;       // blocks of a full-lattice launch
     double* partials;      // scratch: 4 doubles per block
     double* totals;        // scratch: 4 doubles
+    unsigned long long* counts;  // scratch: learned-collide fallback and site counters
+    const lb_mlp* mlp;     // learned collide, or NULL for the plain one
+    float threshold;       // residual above which a site falls back
     bool fused_audit_valid;
     char err[512];
 };
@@ -118,8 +123,9 @@ size_t lb_scratch_bytes(int32_t lx, int32_t ly)
     if (lx < 1 || ly < 1) return 0;
     const int64_t n = (int64_t)lx * ly;
     if (n >= ((int64_t)1 << 31)) return 0;
-    // one partial sum of 4 doubles per row-tiled workgroup, plus the totals
-    return round256((size_t)((int64_t)lx * div_up(ly, BLOCK) * 4 + 4) * sizeof(double));
+    // one partial sum of 4 doubles per row-tiled workgroup, the 4 totals and
+    // two 64-bit counters of the learned collide
+    return round256((size_t)((int64_t)lx * div_up(ly, BLOCK) * 4 + 4 + 2) * sizeof(double));
 }
 
 int lb_init(lb_ctx** out, const lb_config* cfg, const double* rho, const double* ux, const double* uy,
@@ -165,6 +171,9 @@ int lb_init(lb_ctx** out, const lb_config* cfg, const double* rho, const double*
     c->nblocks = (int64_t)k.lx * c->geo.tpr;
     c->partials = (double*)k.scratch;
     c->totals = c->partials + 4 * c->nblocks;
+    c->counts = (unsigned long long*)(c->totals + 4);
+    c->mlp = nullptr;
+    c->threshold = 0.0f;
     c->fused_audit_valid = false;
     c->err[0] = 0;
 
@@ -174,6 +183,11 @@ int lb_init(lb_ctx** out, const lb_config* cfg, const double* rho, const double*
         hipLaunchKernelGGL((k_init<P, L>), grid_of(c), dim3(BLOCK), 0, c->stream, (typename P::T*)k.buf[0],
                            c->geo, rho, ux, uy, T);
     });
+    if (hipMemsetAsync(c->counts, 0, 2 * sizeof(unsigned long long), c->stream) != hipSuccess) {
+        snprintf(g_err, sizeof g_err, "lb_init: clearing the counters failed");
+        delete c;
+        return LB_EDEVICE;
+    }
     const int rc = launch_status(c, "lb_init: launch");
     if (rc != LB_OK) {
         snprintf(g_err, sizeof g_err, "%s", c->err);
@@ -206,16 +220,28 @@ int lb_collide(lb_ctx* c)
     if (!c) return fail(nullptr, LB_EINVAL, "lb_collide: ctx is NULL");
     const double omega = 1.0 / c->cfg.tau;
     const bool comp = c->cfg.compensated != 0;
-    with_config(c->cfg, [&](auto p, auto l) {
-        using P = decltype(p);
-        using L = decltype(l);
-        if (comp)
-            hipLaunchKernelGGL((k_collide<P, L, true>), grid_of(c), dim3(BLOCK), 0, c->stream,
-                               (typename P::T*)cur_buf(c), c->geo, omega);
-        else
-            hipLaunchKernelGGL((k_collide<P, L, false>), grid_of(c), dim3(BLOCK), 0, c->stream,
-                               (typename P::T*)cur_buf(c), c->geo, omega);
-    });
+    if (c->mlp) {
+        with_layout<PrecF32S>(c->cfg.layout, [&](auto, auto l) {
+            using L = decltype(l);
+            if (comp)
+                hipLaunchKernelGGL((k_collide_learned<L, true>), grid_of(c), dim3(BLOCK), 0, c->stream,
+                                   (float*)cur_buf(c), c->geo, omega, c->mlp->net(), c->threshold, c->counts);
+            else
+                hipLaunchKernelGGL((k_collide_learned<L, false>), grid_of(c), dim3(BLOCK), 0, c->stream,
+                                   (float*)cur_buf(c), c->geo, omega, c->mlp->net(), c->threshold, c->counts);
+        });
+    } else {
+        with_config(c->cfg, [&](auto p, auto l) {
+            using P = decltype(p);
+            using L = decltype(l);
+            if (comp)
+                hipLaunchKernelGGL((k_collide<P, L, true>), grid_of(c), dim3(BLOCK), 0, c->stream,
+                                   (typename P::T*)cur_buf(c), c->geo, omega);
+            else
+                hipLaunchKernelGGL((k_collide<P, L, false>), grid_of(c), dim3(BLOCK), 0, c->stream,
+                                   (typename P::T*)cur_buf(c), c->geo, omega);
+        });
+    }
     const int rc = launch_status(c, "lb_collide");
     if (rc != LB_OK) return rc;
     if (c->half_step) {
@@ -235,6 +261,28 @@ int lb_step(lb_ctx* c, int32_t nsteps)
     const bool comp = c->cfg.compensated != 0;
     for (int32_t s = 0; s < nsteps; ++s) {
         const bool audit = c->cfg.audit && s == nsteps - 1;
+        if (c->mlp) {
+            with_layout<PrecF32S>(c->cfg.layout, [&](auto, auto l) {
+                using L = decltype(l);
+                const float* src = (const float*)cur_buf(c);
+                float* dst = (float*)other_buf(c);
+#define D2Q37_LSTEP(CMP, AUD)                                                                                  \
+    hipLaunchKernelGGL((k_step_learned<L, CMP, AUD>), grid_of(c), dim3(BLOCK), 0, c->stream, src, dst, c->geo, \
+                       omega, c->mlp->net(), c->threshold, c->partials, c->counts)
+                if (comp) {
+                    if (audit) D2Q37_LSTEP(true, true); else D2Q37_LSTEP(true, false);
+                } else {
+                    if (audit) D2Q37_LSTEP(false, true); else D2Q37_LSTEP(false, false);
+                }
+#undef D2Q37_LSTEP
+            });
+            const int rc = launch_status(c, "lb_step (learned collide)");
+            if (rc != LB_OK) return rc;
+            c->cur ^= 1;
+            c->steps += 1;
+            c->fused_audit_valid = audit;
+            continue;
+        }
         with_config(c->cfg, [&](auto p, auto l) {
             using P = decltype(p);
             using L = decltype(l);
@@ -327,6 +375,36 @@ int lb_audit(lb_ctx* c, double out[4])
     if (rc != LB_OK) return rc;
     for (int i = 0; i < 4; ++i)
         if (!std::isfinite(out[i])) return fail(c, LB_ENONFINITE, "lb_audit: total %d is not finite", i);
+    return LB_OK;
+}
+
+int lb_set_surrogate(lb_ctx* c, const lb_mlp* m, double threshold)
+{
+    if (!c) return fail(nullptr, LB_EINVAL, "lb_set_surrogate: ctx is NULL");
+    if (!m) {
+        c->mlp = nullptr;
+        return LB_OK;
+    }
+    if (c->cfg.precision != LB_FP32_SHIFTED)
+        return fail(c, LB_EUNSUPPORTED, "lb_set_surrogate: the learned collide needs FP32-shifted populations");
+    if (!(threshold >= 0.0) || !std::isfinite(threshold))
+        return fail(c, LB_EINVAL, "lb_set_surrogate: threshold %g must be finite and >= 0", threshold);
+    c->mlp = m;
+    c->threshold = (float)threshold;
+    return LB_OK;
+}
+
+int lb_surrogate_counts(lb_ctx* c, int64_t out[2])
+{
+    if (!c || !out) return fail(c, LB_EINVAL, "lb_surrogate_counts: NULL argument");
+    unsigned long long h[2];
+    int rc = check_hip(c, hipMemcpyAsync(h, c->counts, sizeof h, hipMemcpyDeviceToHost, c->stream),
+                       "lb_surrogate_counts: copy");
+    if (rc == LB_OK) rc = check_hip(c, hipMemsetAsync(c->counts, 0, sizeof h, c->stream), "lb_surrogate_counts: reset");
+    if (rc == LB_OK) rc = check_hip(c, hipStreamSynchronize(c->stream), "lb_surrogate_counts: synchronize");
+    if (rc != LB_OK) return rc;
+    out[0] = (int64_t)h[0];
+    out[1] = (int64_t)h[1];
     return LB_OK;
 }
 

@@ -1,0 +1,57 @@
+// Host-side state of a learned-collide network (struct lb_mlp of the C ABI):
+// device pointers into the caller's workspace.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+
+#include "mlp_common.hpp"
+
+struct lb_mlp {
+    hipStream_t stream;
+    char* ws;
+    size_t bytes;
+    int32_t max_batch;
+    int32_t max_wg;       // max_batch / samples per training workgroup
+    float* params;        // packed FP32 master parameters
+    float* adam_m;
+    float* adam_v;
+    uint16_t* W1b;
+    uint16_t* W2b;
+    uint16_t* W3b;
+    uint16_t* W2t;
+    uint16_t* W3t;
+    float* norm;          // [4][64]
+    float* partials;      // [max_wg][NPARAM_PAD]
+    double* lossp;        // [max_wg]
+    double* loss_epoch;   // [MAX_EPOCHS][2]: sum, count
+    double* stats;        // [STAT_BLOCKS][74] and means [74]
+    float* grad;          // [NPARAM_PAD]
+    int64_t adam_t;       // Adam steps taken
+    char err[512];
+
+    d2q37::mlp::Net net() const
+    {
+        d2q37::mlp::Net n;
+        n.W1b = W1b;
+        n.W2b = W2b;
+        n.W3b = W3b;
+        n.W2t = W2t;
+        n.W3t = W3t;
+        n.params = params;
+        n.norm = norm;
+        return n;
+    }
+};
+
+namespace d2q37 {
+namespace mlp {
+constexpr int NPARAM_PAD = (NPARAM + 63) / 64 * 64;
+constexpr int TRAIN_SAMPLES = 32;  // samples per training workgroup
+constexpr int MAX_EPOCHS = 4096;
+constexpr int STAT_BLOCKS = 512;
+constexpr int NSTAT = 2 * Q;  // z features then y features
+}  // namespace mlp
+}  // namespace d2q37

@@ -1,0 +1,175 @@
+// Learned collide: shared device pieces of the MLP 37 -> 128 -> 128 -> 37
+// (GELU), run in BF16 on the gfx950 matrix cores with FP32 accumulation.
+//
+// Matrix-core tiles: v_mfma_f32_16x16x32_bf16 computes D(16x16) += A(16x32)
+// B(32x16). Lane l of the wavefront holds
+//   A: row l % 16, columns k = 8 (l / 16) + 0..7      (8 bf16)
+//   B: column l % 16, rows  k = 8 (l / 16) + 0..7      (8 bf16)
+//   D: column l % 16, rows  4 (l / 16) + 0..3          (4 float)
+// so both operands are "16 indices x 32 k" fragments: lane l takes index
+// l % 16 and eight consecutive k. With a matrix stored index-major (k
+// contiguous) a fragment is one 16-byte load per lane.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "lb_collide.hpp"
+
+namespace d2q37 {
+namespace mlp {
+
+constexpr int HID = 128;
+constexpr int KIN = 64;    // input features padded 37 -> 64 (two 32-wide k steps)
+constexpr int NOUT = 48;   // outputs padded 37 -> 48 (three 16-wide tiles)
+// Packed FP32 parameter vector: W1[128][37], b1[128], W2[128][128], b2[128],
+// W3[37][128], b3[37].
+constexpr int OFF_W1 = 0;
+constexpr int OFF_B1 = OFF_W1 + HID * Q;
+constexpr int OFF_W2 = OFF_B1 + HID;
+constexpr int OFF_B2 = OFF_W2 + HID * HID;
+constexpr int OFF_W3 = OFF_B2 + HID;
+constexpr int OFF_B3 = OFF_W3 + Q * HID;
+constexpr int NPARAM = OFF_B3 + Q;  // 26149
+
+constexpr float GELU_C = 0.79788456080286535588f;  // sqrt(2 / pi)
+constexpr float GELU_A = 0.044715f;
+
+typedef __attribute__((__vector_size__(8 * sizeof(__bf16)))) __bf16 bf16x8;
+typedef __attribute__((__vector_size__(4 * sizeof(float)))) float f32x4;
+
+// FP32 -> BF16 bits, round to nearest even (inputs here are finite).
+__device__ inline uint16_t bf16_bits(float f)
+{
+    uint32_t u = __float_as_uint(f);
+    u += 0x7FFFu + ((u >> 16) & 1u);
+    return (uint16_t)(u >> 16);
+}
+__device__ inline float bf16_value(uint16_t b) { return __uint_as_float((uint32_t)b << 16); }
+
+// gelu(a) = 0.5 a (1 + tanh(c (a + A a^3))) written as a / (1 + exp(-2 c (a + A a^3))).
+__device__ inline float gelu(float a)
+{
+    const float y = a * __builtin_fmaf(2.0f * GELU_C * GELU_A, a * a, 2.0f * GELU_C);
+    return a / (1.0f + __expf(-y));
+}
+__device__ inline float gelu_grad(float a)
+{
+    const float y = a * __builtin_fmaf(2.0f * GELU_C * GELU_A, a * a, 2.0f * GELU_C);
+    const float s = 1.0f / (1.0f + __expf(-y));
+    const float dy = __builtin_fmaf(6.0f * GELU_C * GELU_A, a * a, 2.0f * GELU_C);
+    return __builtin_fmaf(a * s * (1.0f - s), dy, s);
+}
+
+__device__ inline int lane_id() { return (int)(threadIdx.x & 63); }
+
+// Fragment (indices i0..i0+15, k0..k0+31) of a matrix stored index-major:
+// element (i, k) at base[i * ld + k]; ld and k0 multiples of 8.
+__device__ inline bf16x8 frag_im(const uint16_t* base, int ld, int i0, int k0)
+{
+    const int l = lane_id();
+    return *(const bf16x8*)(base + (i0 + (l & 15)) * ld + k0 + 8 * (l >> 4));
+}
+// Same fragment of a matrix stored k-major: element (i, k) at base[k * ld + i].
+__device__ inline bf16x8 frag_km(const uint16_t* base, int ld, int i0, int k0)
+{
+    const int l = lane_id();
+    const uint16_t* p = base + (k0 + 8 * (l >> 4)) * ld + i0 + (l & 15);
+    bf16x8 v;
+#pragma unroll
+    for (int j = 0; j < 8; ++j) v[j] = __builtin_bit_cast(__bf16, p[j * ld]);
+    return v;
+}
+
+__device__ inline f32x4 mfma(bf16x8 a, bf16x8 b, f32x4 c)
+{
+    return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
+}
+
+// Device view of a network: BF16 operand copies, FP32 biases (inside the
+// packed parameters) and the standardisation of inputs and outputs.
+struct Net {
+    const uint16_t* W1b;  // [128][64]  W1[h][f], f padded with zeros
+    const uint16_t* W2b;  // [128][128] W2[h2][h1]
+    const uint16_t* W3b;  // [48][128]  W3[o][h], o padded with zeros
+    const uint16_t* W2t;  // [128][128] W2[h2][h1] at [h1][h2]
+    const uint16_t* W3t;  // [128][64]  W3[o][h] at [h][o], o padded
+    const float* params;  // packed FP32 parameters (biases read from here)
+    const float* norm;    // [4][64]: mean z, 1/sd z, mean y, sd y
+};
+
+// ---- conserved part and residual of shifted populations -----------------------
+// The four conserved functions phi = 1, xi_x, xi_y, xi^2 - 2 have Gram matrix
+// sum_p w_p phi_a phi_b = diag(1, 1, 1, 4) on the D2Q37 quadrature, so the
+// projection of g onto w * phi (in the 1/w inner product) has coefficients
+// (sum g, sum g xi_x, sum g xi_y, sum g (xi^2 - 2) / 4).
+struct Conserved {
+    float m0, mx, my, mE;
+};
+
+__device__ inline Conserved conserved_moments(const float (&g)[Q])
+{
+    float m0 = 0.f, jx = 0.f, jy = 0.f, e = 0.f;
+#pragma unroll
+    for (int p = 0; p < Q; ++p) {
+        m0 += g[p];
+        if (CX[p] != 0) jx = __builtin_fmaf((float)CX[p], g[p], jx);
+        if (CY[p] != 0) jy = __builtin_fmaf((float)CY[p], g[p], jy);
+        if (c2_of(p) != 0) e = __builtin_fmaf((float)c2_of(p), g[p], e);
+    }
+    Conserved c;
+    c.m0 = m0;
+    c.mx = mulk(jx, R);
+    c.my = mulk(jy, R);
+    c.mE = mulk(e, R2) - 2.0f * m0;
+    return c;
+}
+
+// Coefficients of a conserved-space vector w_p (a0 + ax xi_px + ay xi_py +
+// aE (xi_p^2 - 2) / 4), pre-scaled so that each population needs integer
+// multiples only: v_p = c0 + cx cx_p + cy cy_p + cq |c_p|^2, times w_p. The
+// model constants enter through hi + lo products (mulk), so the moments of
+// the vector are exact to FP32 rounding of the sums.
+struct ConservedCoef {
+    float c0, cx, cy, cq;
+};
+__device__ inline ConservedCoef conserved_coef(float a0, float ax, float ay, float aE)
+{
+    ConservedCoef k;
+    k.c0 = a0 - 0.5f * aE;
+    k.cx = mulk(ax, R);
+    k.cy = mulk(ay, R);
+    k.cq = mulk(0.25f * aE, R2);
+    return k;
+}
+__device__ inline float conserved_value(int p, const ConservedCoef& k)
+{
+    float v = k.c0;
+    if (CX[p] != 0) v = __builtin_fmaf(k.cx, (float)CX[p], v);
+    if (CY[p] != 0) v = __builtin_fmaf(k.cy, (float)CY[p], v);
+    if (c2_of(p) != 0) v = __builtin_fmaf(k.cq, (float)c2_of(p), v);
+    return mulk(v, weight(p));
+}
+
+// ---- features of a training pair --------------------------------------------------
+// z = pre / w; y = (g_eq - P(pre)) / w with g_eq = pre + tau (post - pre).
+__device__ inline void pair_features(const float* pre_row, const float* post_row, float tau, float (&z)[Q],
+                                     float (&y)[Q])
+{
+    float g[Q];
+#pragma unroll
+    for (int p = 0; p < Q; ++p) g[p] = pre_row[p];
+    const Conserved m = conserved_moments(g);
+    const ConservedCoef k = conserved_coef(m.m0, m.mx, m.my, m.mE);
+#pragma unroll
+    for (int p = 0; p < Q; ++p) {
+        const float inv_w = (float)(1.0 / weight(p));
+        const float geq = __builtin_fmaf(tau, post_row[p] - g[p], g[p]);
+        z[p] = g[p] * inv_w;
+        y[p] = (geq - conserved_value(p, k)) * inv_w;
+    }
+}
+
+}  // namespace mlp
+}  // namespace d2q37

@@ -73,6 +73,24 @@ _SIGNATURES = {
     "lb_last_error": (ctypes.c_char_p, [_VP]),
     "lb_model_constants": (ctypes.c_int, [ctypes.POINTER(_D), ctypes.POINTER(_D), ctypes.POINTER(_I32)]),
     "lb_copy": (ctypes.c_int, [_VP, _VP, _SZ, _VP]),
+    "lb_mlp_param_count": (_SZ, []),
+    "lb_mlp_workspace_bytes": (_SZ, [_I32]),
+    "lb_mlp_create": (ctypes.c_int, [ctypes.POINTER(_VP), _VP, _SZ, _I32, _VP]),
+    "lb_mlp_destroy": (None, [_VP]),
+    "lb_mlp_last_error": (ctypes.c_char_p, [_VP]),
+    "lb_mlp_init": (ctypes.c_int, [_VP, ctypes.c_uint64]),
+    "lb_mlp_set_params": (ctypes.c_int, [_VP, _VP]),
+    "lb_mlp_get_params": (ctypes.c_int, [_VP, _VP]),
+    "lb_mlp_set_normalization": (ctypes.c_int, [_VP, _VP]),
+    "lb_mlp_get_normalization": (ctypes.c_int, [_VP, _VP]),
+    "lb_mlp_fit_normalization": (ctypes.c_int, [_VP, _VP, _VP, _I64, _D]),
+    "lb_mlp_gradient": (ctypes.c_int, [_VP, _VP, _VP, _I32, _D, _VP, ctypes.POINTER(_D)]),
+    "lb_mlp_train": (ctypes.c_int, [_VP, _VP, _VP, _I64, _D, _I32, _I32, ctypes.c_float, ctypes.c_uint64, _I64,
+                                    _VP]),
+    "lb_mlp_equilibrium": (ctypes.c_int, [_VP, _VP, _I64, ctypes.c_float, _VP, _VP, _VP]),
+    "lb_pairgen": (ctypes.c_int, [_VP, _VP, _I64, ctypes.c_uint64, _D, _VP]),
+    "lb_set_surrogate": (ctypes.c_int, [_VP, _VP, _D]),
+    "lb_surrogate_counts": (ctypes.c_int, [_VP, _VP]),
 }
 
 
@@ -128,6 +146,122 @@ def device_copy(dst, src, stream=None):
     s = stream if stream is not None else torch.cuda.current_stream()
     nbytes = src.numel() * src.element_size()
     _check(lib().lb_copy(dst.data_ptr(), src.data_ptr(), nbytes, s.cuda_stream), None, "lb_copy")
+
+
+NPARAM = 26149
+
+
+def pairgen(n: int, seed: int, tau: float, device: str = "cuda"):
+    """n training pairs (pre, post) of shifted FP32 populations, (n, 37) each,
+    drawn on the GPU."""
+    torch = _torch()
+    pre = torch.empty((n, Q), dtype=torch.float32, device=device)
+    post = torch.empty_like(pre)
+    _check(lib().lb_pairgen(pre.data_ptr(), post.data_ptr(), n, seed, tau, torch.cuda.current_stream().cuda_stream),
+           None, "lb_pairgen")
+    return pre, post
+
+
+def _pairs_arg(t, name: str):
+    """A device FP32 (n, 37) tensor in row-major order (copied if needed)."""
+    torch = _torch()
+    if not isinstance(t, torch.Tensor) or t.device.type != "cuda":
+        raise TypeError(f"{name} must be a CUDA tensor")
+    if t.dtype != torch.float32 or t.dim() != 2 or t.shape[1] != Q:
+        raise ValueError(f"{name} must be float32 of shape (n, {Q}), got {t.dtype} {tuple(t.shape)}")
+    return t.contiguous()
+
+
+def _mcheck(rc, m, what):
+    if rc != LB_OK:
+        raise LBError(rc, f"{what}: {lib().lb_mlp_last_error(m).decode(errors='replace')}")
+
+
+class Mlp:
+    """The learned-collide network (37-128-128-37, GELU) in a PyTorch-owned
+    device workspace; every computation runs in libd2q37's kernels."""
+
+    def __init__(self, max_batch: int = 8192, device: str = "cuda"):
+        torch = _torch()
+        self.max_batch = int(max_batch)
+        nbytes = lib().lb_mlp_workspace_bytes(self.max_batch)
+        if nbytes == 0:
+            raise LBError(LB_EINVAL, f"invalid max_batch {max_batch}")
+        self.ws = torch.empty(nbytes, dtype=torch.uint8, device=device)
+        self.stream = torch.cuda.current_stream()
+        self._m = ctypes.c_void_p()
+        _mcheck(lib().lb_mlp_create(ctypes.byref(self._m), self.ws.data_ptr(), nbytes, self.max_batch,
+                                    self.stream.cuda_stream), None, "lb_mlp_create")
+
+    @property
+    def handle(self):
+        if self._m is None or not self._m.value:
+            raise RuntimeError("network is closed")
+        return self._m
+
+    def init(self, seed: int):
+        _mcheck(lib().lb_mlp_init(self.handle, seed), self.handle, "lb_mlp_init")
+
+    def set_params(self, theta):
+        a = np.ascontiguousarray(theta, dtype=np.float32)
+        assert a.size == NPARAM
+        _mcheck(lib().lb_mlp_set_params(self.handle, a.ctypes.data), self.handle, "lb_mlp_set_params")
+
+    def get_params(self) -> np.ndarray:
+        a = np.empty(NPARAM, dtype=np.float32)
+        _mcheck(lib().lb_mlp_get_params(self.handle, a.ctypes.data), self.handle, "lb_mlp_get_params")
+        return a
+
+    def set_normalization(self, norm):
+        a = np.ascontiguousarray(norm, dtype=np.float32).reshape(4, Q)
+        _mcheck(lib().lb_mlp_set_normalization(self.handle, a.ctypes.data), self.handle, "lb_mlp_set_normalization")
+
+    def get_normalization(self) -> np.ndarray:
+        a = np.empty((4, Q), dtype=np.float32)
+        _mcheck(lib().lb_mlp_get_normalization(self.handle, a.ctypes.data), self.handle, "lb_mlp_get_normalization")
+        return a
+
+    def fit_normalization(self, pre, post, tau: float):
+        pre, post = _pairs_arg(pre, "pre"), _pairs_arg(post, "post")
+        _mcheck(lib().lb_mlp_fit_normalization(self.handle, pre.data_ptr(), post.data_ptr(), pre.shape[0], tau),
+                self.handle, "lb_mlp_fit_normalization")
+
+    def gradient(self, pre, post, tau: float):
+        pre, post = _pairs_arg(pre, "pre"), _pairs_arg(post, "post")
+        g = np.empty(NPARAM, dtype=np.float32)
+        loss = ctypes.c_double()
+        _mcheck(lib().lb_mlp_gradient(self.handle, pre.data_ptr(), post.data_ptr(), pre.shape[0], tau,
+                                      g.ctypes.data, ctypes.byref(loss)), self.handle, "lb_mlp_gradient")
+        return g, loss.value
+
+    def train(self, pre, post, tau: float, batch: int, epochs: int, lr: float, seed: int, max_steps: int = 0):
+        pre, post = _pairs_arg(pre, "pre"), _pairs_arg(post, "post")
+        losses = np.zeros(epochs)
+        _mcheck(lib().lb_mlp_train(self.handle, pre.data_ptr(), post.data_ptr(), pre.shape[0], tau, batch, epochs,
+                                   lr, seed, max_steps, losses.ctypes.data), self.handle, "lb_mlp_train")
+        return losses
+
+    def equilibrium(self, pre, threshold: float):
+        torch = _torch()
+        pre = _pairs_arg(pre, "pre")
+        n = pre.shape[0]
+        geq = torch.empty_like(pre)
+        res = torch.empty(n, dtype=torch.float32, device=pre.device)
+        fb = torch.empty(n, dtype=torch.int32, device=pre.device)
+        _mcheck(lib().lb_mlp_equilibrium(self.handle, pre.data_ptr(), n, threshold, geq.data_ptr(), res.data_ptr(),
+                                         fb.data_ptr()), self.handle, "lb_mlp_equilibrium")
+        return geq, res, fb
+
+    def close(self):
+        if self._m is not None and self._m.value:
+            lib().lb_mlp_destroy(self._m)
+        self._m = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 class Lattice:
@@ -223,6 +357,18 @@ class Lattice:
             raise LBNonFinite(rc, lib().lb_last_error(self.ctx).decode(), vals)
         _check(rc, self.ctx, "lb_audit")
         return vals
+
+    def set_surrogate(self, mlp, threshold: float = 1e-3):
+        """Collide with the network (FP32-shifted lattices); None restores the
+        plain collide."""
+        self._mlp = mlp
+        _check(lib().lb_set_surrogate(self.ctx, mlp.handle if mlp is not None else None, threshold), self.ctx,
+               "lb_set_surrogate")
+
+    def surrogate_counts(self):
+        out = (ctypes.c_int64 * 2)()
+        _check(lib().lb_surrogate_counts(self.ctx, out), self.ctx, "lb_surrogate_counts")
+        return int(out[0]), int(out[1])
 
     def current_buffer(self) -> int:
         return lib().lb_current_buffer(self.ctx)
