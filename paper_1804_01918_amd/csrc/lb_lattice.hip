@@ -29,6 +29,9 @@ struct lb_ctx {
     unsigned long long* counts;  // scratch: learned-collide fallback and site counters
     const lb_mlp* mlp;     // learned collide, or NULL for the plain one
     float threshold;       // residual above which a site falls back
+    Geo lgeo;              // geometry of the learned kernels (512-site tiles)
+    int lgrid;             // their persistent grid: min(tiles, compute units)
+    int64_t audit_parts;   // partial sums written by the last fused audit
     bool fused_audit_valid;
     char err[512];
 };
@@ -100,6 +103,7 @@ void* other_buf(lb_ctx* c) { return c->cfg.buf[c->cur ^ 1]; }
 int launch_status(lb_ctx* c, const char* what) { return check_hip(c, hipGetLastError(), what); }
 
 dim3 grid_of(const lb_ctx* c) { return dim3((unsigned)c->nblocks); }
+dim3 lgrid_of(const lb_ctx* c) { return dim3((unsigned)c->lgrid); }
 
 }  // namespace
 
@@ -174,6 +178,9 @@ int lb_init(lb_ctx** out, const lb_config* cfg, const double* rho, const double*
     c->counts = (unsigned long long*)(c->totals + 4);
     c->mlp = nullptr;
     c->threshold = 0.0f;
+    c->lgeo = c->geo;
+    c->lgrid = 1;
+    c->audit_parts = c->nblocks;
     c->fused_audit_valid = false;
     c->err[0] = 0;
 
@@ -224,11 +231,11 @@ int lb_collide(lb_ctx* c)
         with_layout<PrecF32S>(c->cfg.layout, [&](auto, auto l) {
             using L = decltype(l);
             if (comp)
-                hipLaunchKernelGGL((k_collide_learned<L, true>), grid_of(c), dim3(BLOCK), 0, c->stream,
-                                   (float*)cur_buf(c), c->geo, omega, c->mlp->net(), c->threshold, c->counts);
+                hipLaunchKernelGGL((k_collide_learned<L, true>), lgrid_of(c), dim3(LBLOCK), 0, c->stream,
+                                   (float*)cur_buf(c), c->lgeo, omega, c->mlp->net(), c->threshold, c->counts);
             else
-                hipLaunchKernelGGL((k_collide_learned<L, false>), grid_of(c), dim3(BLOCK), 0, c->stream,
-                                   (float*)cur_buf(c), c->geo, omega, c->mlp->net(), c->threshold, c->counts);
+                hipLaunchKernelGGL((k_collide_learned<L, false>), lgrid_of(c), dim3(LBLOCK), 0, c->stream,
+                                   (float*)cur_buf(c), c->lgeo, omega, c->mlp->net(), c->threshold, c->counts);
         });
     } else {
         with_config(c->cfg, [&](auto p, auto l) {
@@ -267,7 +274,7 @@ int lb_step(lb_ctx* c, int32_t nsteps)
                 const float* src = (const float*)cur_buf(c);
                 float* dst = (float*)other_buf(c);
 #define D2Q37_LSTEP(CMP, AUD)                                                                                  \
-    hipLaunchKernelGGL((k_step_learned<L, CMP, AUD>), grid_of(c), dim3(BLOCK), 0, c->stream, src, dst, c->geo, \
+    hipLaunchKernelGGL((k_step_learned<L, CMP, AUD>), lgrid_of(c), dim3(LBLOCK), 0, c->stream, src, dst, c->lgeo, \
                        omega, c->mlp->net(), c->threshold, c->partials, c->counts)
                 if (comp) {
                     if (audit) D2Q37_LSTEP(true, true); else D2Q37_LSTEP(true, false);
@@ -281,6 +288,7 @@ int lb_step(lb_ctx* c, int32_t nsteps)
             c->cur ^= 1;
             c->steps += 1;
             c->fused_audit_valid = audit;
+            if (audit) c->audit_parts = c->lgrid;
             continue;
         }
         with_config(c->cfg, [&](auto p, auto l) {
@@ -303,6 +311,7 @@ int lb_step(lb_ctx* c, int32_t nsteps)
         c->cur ^= 1;
         c->steps += 1;
         c->fused_audit_valid = audit;
+        if (audit) c->audit_parts = c->nblocks;
     }
     return LB_OK;
 }
@@ -364,8 +373,9 @@ int lb_audit(lb_ctx* c, double out[4])
     const double n = (double)c->geo.n;
     const bool shifted = c->cfg.precision != LB_FP64;
     const double4 base = shifted ? double4{n, 0.0, 0.0, n} : double4{0.0, 0.0, 0.0, 0.0};
-    hipLaunchKernelGGL(k_audit_final, dim3(1), dim3(BLOCK), 0, c->stream, (const double*)c->partials,
-                       (int64_t)c->nblocks, base, c->totals);
+    const int64_t nparts = c->fused_audit_valid ? c->audit_parts : c->nblocks;
+    hipLaunchKernelGGL(k_audit_final, dim3(1), dim3(BLOCK), 0, c->stream, (const double*)c->partials, nparts, base,
+                       c->totals);
     int rc = launch_status(c, "lb_audit: final");
     if (rc != LB_OK) return rc;
     rc = check_hip(c, hipMemcpyAsync(out, c->totals, 4 * sizeof(double), hipMemcpyDeviceToHost, c->stream),
@@ -389,6 +399,14 @@ int lb_set_surrogate(lb_ctx* c, const lb_mlp* m, double threshold)
         return fail(c, LB_EUNSUPPORTED, "lb_set_surrogate: the learned collide needs FP32-shifted populations");
     if (!(threshold >= 0.0) || !std::isfinite(threshold))
         return fail(c, LB_EINVAL, "lb_set_surrogate: threshold %g must be finite and >= 0", threshold);
+    int dev = 0, ncu = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || ncu < 1)
+        return fail(c, LB_EDEVICE, "lb_set_surrogate: cannot query the compute-unit count");
+    c->lgeo = c->geo;
+    c->lgeo.tpr = (int)div_up(c->geo.ly, LBLOCK);
+    const int64_t tiles = (int64_t)c->geo.lx * c->lgeo.tpr;
+    c->lgrid = (int)std::min<int64_t>(tiles, ncu);
     c->mlp = m;
     c->threshold = (float)threshold;
     return LB_OK;

@@ -2,6 +2,13 @@
 // step and the in-place collide with the network's equilibrium, falling back
 // per site to the plain FP32 collide; fallback and site counts are
 // accumulated in two 64-bit counters.
+//
+// Persistent launch: one 512-lane workgroup per compute unit copies the BF16
+// weights into LDS once and then walks 512-site row tiles (a tile is a run
+// of one lattice row; the tiles of an XCD are contiguous). Each wavefront
+// stages its 64 sites' inputs in its own LDS rows, runs the network, then
+// gathers the populations a second time (cache hits) for the projection,
+// the fallback verdict and the relaxation.
 #pragma once
 
 #include "lb_kernels.hpp"
@@ -9,77 +16,163 @@
 
 namespace d2q37 {
 
-__device__ inline void count_sites(bool fallback, bool active, unsigned long long* counts)
+constexpr int LBLOCK = 512;
+constexpr int LWAVES = LBLOCK / 64;
+
+struct LearnedLds {
+    mlp::SharedWeights w;
+    uint16_t X[LWAVES][mlp::WAVE_LDS_BYTES / 2];
+    double red[LWAVES][4];
+};
+
+// Tiles [first, end) with stride step visited by this workgroup.
+struct TileWalk {
+    int64_t first, end, step;
+};
+__device__ inline TileWalk tile_walk(int64_t ntiles)
 {
-    const unsigned long long mfb = __ballot(fallback), mact = __ballot(active);
-    if ((threadIdx.x & 63) == 0) {
-        atomicAdd(&counts[0], (unsigned long long)__popcll(mfb));
-        atomicAdd(&counts[1], (unsigned long long)__popcll(mact));
+    const int64_t G = gridDim.x, b = blockIdx.x;
+    if (G < 8) return {b, ntiles, G};
+    const int64_t xcd = b % 8, idx = b / 8;
+    const int64_t nwg = (G - xcd + 7) / 8;  // workgroups dealt to this XCD
+    const int64_t lo = xcd * ntiles / 8, hi = (xcd + 1) * ntiles / 8;
+    return {lo + idx, hi, nwg};
+}
+
+template <bool AUDIT>
+__device__ inline void finish_learned(LearnedLds& S, double (&acc)[4], unsigned long long nfb,
+                                      unsigned long long nact, double* partials, unsigned long long* counts)
+{
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    if (lane == 0) {
+        atomicAdd(&counts[0], nfb);
+        atomicAdd(&counts[1], nact);
+    }
+    if constexpr (AUDIT) {
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+#pragma unroll
+            for (int off = 32; off >= 1; off >>= 1) acc[k] += __shfl_xor(acc[k], off, 64);
+        }
+        if (lane == 0) {
+#pragma unroll
+            for (int k = 0; k < 4; ++k) S.red[wave][k] = acc[k];
+        }
+        __syncthreads();
+        if (threadIdx.x == 0) {
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                double s = S.red[0][k];
+                for (int w = 1; w < LWAVES; ++w) s += S.red[w][k];
+                partials[4 * blockIdx.x + k] = s;
+            }
+        }
     }
 }
 
-// Fused step src -> dst with the learned collide. Every wavefront runs the
-// network (inactive lanes carry zeros), so no lane returns early.
+// Fused step src -> dst with the learned collide; g.tpr counts 512-site
+// tiles per row here. With AUDIT, partials[4 * blockIdx.x ..] receive the
+// workgroup's FP64 sums.
 template <class L, bool COMP, bool AUDIT>
-__global__ __launch_bounds__(BLOCK) void k_step_learned(const float* __restrict__ src, float* __restrict__ dst, Geo g,
-                                                        double omega, mlp::Net net, float threshold,
-                                                        double* __restrict__ partials,
-                                                        unsigned long long* __restrict__ counts)
+__global__ __launch_bounds__(LBLOCK) __attribute__((amdgpu_waves_per_eu(2, 2))) void k_step_learned(
+    const float* __restrict__ src, float* __restrict__ dst, Geo g, double omega, mlp::Net gnet, float threshold,
+    double* __restrict__ partials, unsigned long long* __restrict__ counts)
 {
     using P = PrecF32S;
-    D2Q37_SITE(P, L);
-    __shared__ uint16_t lds[BLOCK / 64][mlp::WAVE_LDS_BYTES / 2];
-    float v[Q];
-#pragma unroll
-    for (int p = 0; p < Q; ++p) v[p] = active ? P::template load<L::stream_loads>(st.src(src, p, g), p) : 0.0f;
-    float ghat[Q];
-    const mlp::Verdict vd = mlp::learned_equilibrium(v, net, lds[threadIdx.x >> 6], threshold, ghat);
-    const bool fb = active && vd.fallback;
+    constexpr int VL = vl_of<P>();
+    __shared__ LearnedLds S;
+    const mlp::Net net = mlp::share_weights<LBLOCK>(gnet, S.w);
+    __syncthreads();
+    uint16_t* X = S.X[threadIdx.x >> 6];
+    const float om = (float)omega;
     double acc[4] = {0.0, 0.0, 0.0, 0.0};
-    if (active) {
-        double d[Q];
-        auto store = [&](int p, float r) {
-            P::template store<L::stream_stores>(st.own(dst, p, g), p, r);
-            if constexpr (AUDIT) d[p] = (double)r;
-        };
-        const float om = (float)omega;
-        if (fb) {
-            collide_site<P, COMP>(v, om, store);
-        } else {
+    unsigned long long nfb = 0, nact = 0;
+    const TileWalk tw = tile_walk((int64_t)g.lx * g.tpr);
+    for (int64_t tile = tw.first; tile < tw.end; tile += tw.step) {
+        const int xrow = (int)(tile / g.tpr);
+        const int r = (int)(tile - (int64_t)xrow * g.tpr) * LBLOCK + (int)threadIdx.x;
+        const bool active = r < g.ly;
+        Stencil<L, float, VL> st;
+        if (active) st.setup(xrow, r, g);
+        // first gather: standardised network inputs (loads that keep the lines cached)
 #pragma unroll
-            for (int p = 0; p < Q; ++p) store(p, __builtin_fmaf(om, ghat[p] - v[p], v[p]));
+        for (int p = 0; p < Q; ++p)
+            mlp::stage_input(X, net, p, active ? P::template load<false>(st.src(src, p, g), p) : 0.0f);
+        mlp::stage_padding(X);
+        mlp::network_outputs(net, X);
+        // second gather: the populations for projection and relaxation
+        float v[Q];
+#pragma unroll
+        for (int p = 0; p < Q; ++p) v[p] = active ? P::template load<L::stream_loads>(st.src(src, p, g), p) : 0.0f;
+        const mlp::Learned lr = mlp::learned_equilibrium(v, net, X, threshold);
+        const bool fb = active && lr.verdict.fallback;
+        if (active) {
+            double d[Q];
+            auto store = [&](int p, float res) {
+                P::template store<L::stream_stores>(st.own(dst, p, g), p, res);
+                if constexpr (AUDIT) d[p] = (double)res;
+            };
+            if (fb) {
+                collide_site<P, COMP>(v, om, store);
+            } else {
+#pragma unroll
+                for (int p = 0; p < Q; ++p) store(p, __builtin_fmaf(om, mlp::learned_value(lr, net, p) - v[p], v[p]));
+            }
+            if constexpr (AUDIT) audit_site(d, acc);
         }
-        if constexpr (AUDIT) audit_site(d, acc);
+        nfb += __popcll(__ballot(fb));
+        nact += __popcll(__ballot(active));
+        mlp::wave_sync();  // the staged rows are reused by the next tile
     }
-    count_sites(fb, active, counts);
-    if constexpr (AUDIT) block_reduce4(acc, partials + 4 * tile);
+    finish_learned<AUDIT>(S, acc, nfb, nact, partials, counts);
 }
 
-// In-place learned collide on the current buffer.
+// In-place learned collide on the current buffer (same walk).
 template <class L, bool COMP>
-__global__ __launch_bounds__(BLOCK) void k_collide_learned(float* __restrict__ buf, Geo g, double omega, mlp::Net net,
-                                                           float threshold, unsigned long long* __restrict__ counts)
+__global__ __launch_bounds__(LBLOCK) __attribute__((amdgpu_waves_per_eu(2, 2))) void k_collide_learned(
+    float* __restrict__ buf, Geo g, double omega, mlp::Net gnet, float threshold,
+    unsigned long long* __restrict__ counts)
 {
     using P = PrecF32S;
-    D2Q37_SITE(P, L);
-    __shared__ uint16_t lds[BLOCK / 64][mlp::WAVE_LDS_BYTES / 2];
-    float v[Q];
+    constexpr int VL = vl_of<P>();
+    __shared__ LearnedLds S;
+    const mlp::Net net = mlp::share_weights<LBLOCK>(gnet, S.w);
+    __syncthreads();
+    uint16_t* X = S.X[threadIdx.x >> 6];
+    const float om = (float)omega;
+    double acc[4] = {0.0, 0.0, 0.0, 0.0};
+    unsigned long long nfb = 0, nact = 0;
+    const TileWalk tw = tile_walk((int64_t)g.lx * g.tpr);
+    for (int64_t tile = tw.first; tile < tw.end; tile += tw.step) {
+        const int xrow = (int)(tile / g.tpr);
+        const int r = (int)(tile - (int64_t)xrow * g.tpr) * LBLOCK + (int)threadIdx.x;
+        const bool active = r < g.ly;
+        Stencil<L, float, VL> st;
+        if (active) st.setup(xrow, r, g);
 #pragma unroll
-    for (int p = 0; p < Q; ++p) v[p] = active ? P::template load<L::stream_loads>(st.own(buf, p, g), p) : 0.0f;
-    float ghat[Q];
-    const mlp::Verdict vd = mlp::learned_equilibrium(v, net, lds[threadIdx.x >> 6], threshold, ghat);
-    const bool fb = active && vd.fallback;
-    if (active) {
-        auto store = [&](int p, float r) { P::template store<L::stream_stores>(st.own(buf, p, g), p, r); };
-        const float om = (float)omega;
-        if (fb) {
-            collide_site<P, COMP>(v, om, store);
-        } else {
+        for (int p = 0; p < Q; ++p)
+            mlp::stage_input(X, net, p, active ? P::template load<false>(st.own(buf, p, g), p) : 0.0f);
+        mlp::stage_padding(X);
+        mlp::network_outputs(net, X);
+        float v[Q];
 #pragma unroll
-            for (int p = 0; p < Q; ++p) store(p, __builtin_fmaf(om, ghat[p] - v[p], v[p]));
+        for (int p = 0; p < Q; ++p) v[p] = active ? P::template load<L::stream_loads>(st.own(buf, p, g), p) : 0.0f;
+        const mlp::Learned lr = mlp::learned_equilibrium(v, net, X, threshold);
+        const bool fb = active && lr.verdict.fallback;
+        if (active) {
+            auto store = [&](int p, float res) { P::template store<L::stream_stores>(st.own(buf, p, g), p, res); };
+            if (fb) {
+                collide_site<P, COMP>(v, om, store);
+            } else {
+#pragma unroll
+                for (int p = 0; p < Q; ++p) store(p, __builtin_fmaf(om, mlp::learned_value(lr, net, p) - v[p], v[p]));
+            }
         }
+        nfb += __popcll(__ballot(fb));
+        nact += __popcll(__ballot(active));
+        mlp::wave_sync();
     }
-    count_sites(fb, active, counts);
+    finish_learned<false>(S, acc, nfb, nact, nullptr, counts);
 }
 
 }  // namespace d2q37

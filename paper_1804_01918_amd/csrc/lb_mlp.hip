@@ -115,9 +115,18 @@ __global__ __launch_bounds__(TB) void k_mlp_init(float* __restrict__ params, uin
 // BF16 operand copies of the weights, zero padding included.
 __global__ __launch_bounds__(TB) void k_mlp_pack(const float* __restrict__ params, uint16_t* __restrict__ W1b,
                                                  uint16_t* __restrict__ W2b, uint16_t* __restrict__ W3b,
-                                                 uint16_t* __restrict__ W2t, uint16_t* __restrict__ W3t)
+                                                 uint16_t* __restrict__ W2t, uint16_t* __restrict__ W3t,
+                                                 uint16_t* __restrict__ W2p, uint16_t* __restrict__ W3p)
 {
     const int i = blockIdx.x * TB + threadIdx.x;
+    if (i < HID * HID) {  // W2p[h2][slot]
+        const int a = i / HID, slot = i % HID;
+        W2p[i] = bf16_bits(params[OFF_W2 + a * HID + chain_hidden(slot)]);
+    }
+    if (i < NOUT * HID) {  // W3p[o][slot]
+        const int o = i / HID, slot = i % HID;
+        W3p[i] = o < Q ? bf16_bits(params[OFF_W3 + o * HID + chain_hidden(slot)]) : 0;
+    }
     if (i < HID * KIN) {  // W1b[h][f], W3t[h][o]
         const int h = i / KIN, f = i % KIN;
         W1b[i] = f < Q ? bf16_bits(params[OFF_W1 + h * Q + f]) : 0;
@@ -405,7 +414,8 @@ __global__ __launch_bounds__(TB) void k_mlp_update(float* __restrict__ params, f
                                                    double* __restrict__ loss_epoch, int epoch,
                                                    uint16_t* __restrict__ W1b, uint16_t* __restrict__ W2b,
                                                    uint16_t* __restrict__ W3b, uint16_t* __restrict__ W2t,
-                                                   uint16_t* __restrict__ W3t)
+                                                   uint16_t* __restrict__ W3t, uint16_t* __restrict__ W2p,
+                                                   uint16_t* __restrict__ W3p)
 {
     const int i = blockIdx.x * TB + threadIdx.x;
     if (blockIdx.x == 0 && threadIdx.x == 0 && loss_epoch) {
@@ -436,36 +446,43 @@ __global__ __launch_bounds__(TB) void k_mlp_update(float* __restrict__ params, f
         const int j = i - OFF_W2, h2 = j / HID, h1 = j % HID;
         W2b[h2 * HID + h1] = b;
         W2t[h1 * HID + h2] = b;
+        W2p[h2 * HID + chain_slot(h1)] = b;
     } else if (i >= OFF_W3 && i < OFF_B3) {
         const int j = i - OFF_W3, o = j / HID, h = j % HID;
         W3b[o * HID + h] = b;
         W3t[h * KIN + o] = b;
+        W3p[o * HID + chain_slot(h)] = b;
     }
 }
 
 // Learned equilibrium of n shifted-population sites (one per lane), with the
 // plain equilibrium where the verdict is fallback.
-__global__ __launch_bounds__(TB) void k_mlp_eval(const float* __restrict__ pre, int64_t n, Net net, float threshold,
+__global__ __launch_bounds__(TB) __attribute__((amdgpu_waves_per_eu(2, 2))) void k_mlp_eval(const float* __restrict__ pre, int64_t n, Net net, float threshold,
                                                  float* __restrict__ geq, float* __restrict__ res,
                                                  int32_t* __restrict__ fb)
 {
     __shared__ uint16_t lds[TB / 64][WAVE_LDS_BYTES / 2];
+    uint16_t* X = lds[threadIdx.x >> 6];
     const int64_t s = (int64_t)blockIdx.x * TB + threadIdx.x;
     const bool active = s < n;
+#pragma unroll
+    for (int p = 0; p < Q; ++p) stage_input(X, net, p, active ? pre[s * Q + p] : 0.0f);
+    stage_padding(X);
+    network_outputs(net, X);
     float g[Q];
 #pragma unroll
     for (int p = 0; p < Q; ++p) g[p] = active ? pre[s * Q + p] : 0.0f;
-    float ghat[Q];
-    const Verdict vd = learned_equilibrium(g, net, lds[threadIdx.x >> 6], threshold, ghat);
+    const Learned lr = learned_equilibrium(g, net, X, threshold);
     if (!active) return;
-    if (vd.fallback) {
+    if (lr.verdict.fallback) {
         const Macro<float> m = macro_from_raw<float, true>(raw_moments_compensated(g));
-        relax_emit<float, true>(g, m, 1.0f, 0.0f, [&](int p, float v) { ghat[p] = v; });
-    }
+        relax_emit<float, true>(g, m, 1.0f, 0.0f, [&](int p, float v) { geq[s * Q + p] = v; });
+    } else {
 #pragma unroll
-    for (int p = 0; p < Q; ++p) geq[s * Q + p] = ghat[p];
-    if (res) res[s] = vd.residual;
-    if (fb) fb[s] = vd.fallback ? 1 : 0;
+        for (int p = 0; p < Q; ++p) geq[s * Q + p] = learned_value(lr, net, p);
+    }
+    if (res) res[s] = lr.verdict.residual;
+    if (fb) fb[s] = lr.verdict.fallback ? 1 : 0;
 }
 
 // ---- host side ----------------------------------------------------------------------
@@ -492,7 +509,7 @@ int mcheck(lb_mlp* m, const char* what)
 size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
 
 struct WsLayout {
-    size_t params, m, v, W1b, W2b, W3b, W2t, W3t, norm, partials, lossp, loss_epoch, stats, grad, total;
+    size_t params, m, v, W1b, W2b, W3b, W2t, W3t, W2p, W3p, norm, partials, lossp, loss_epoch, stats, grad, total;
 };
 
 WsLayout workspace_layout(int max_batch)
@@ -513,6 +530,8 @@ WsLayout workspace_layout(int max_batch)
     l.W3b = take(NOUT * HID * 2);
     l.W2t = take(HID * HID * 2);
     l.W3t = take(HID * KIN * 2);
+    l.W2p = take(HID * HID * 2);
+    l.W3p = take(NOUT * HID * 2);
     l.norm = take(4 * 64 * 4);
     l.partials = take((size_t)max_wg * NPARAM_PAD * 4);
     l.lossp = take((size_t)max_wg * 8);
@@ -526,7 +545,7 @@ WsLayout workspace_layout(int max_batch)
 int launch_pack(lb_mlp* m)
 {
     hipLaunchKernelGGL(k_mlp_pack, dim3((HID * HID + TB - 1) / TB), dim3(TB), 0, m->stream, m->params, m->W1b, m->W2b,
-                       m->W3b, m->W2t, m->W3t);
+                       m->W3b, m->W2t, m->W3t, m->W2p, m->W3p);
     return mcheck(m, "pack");
 }
 
@@ -625,6 +644,8 @@ int lb_mlp_create(lb_mlp** out, void* workspace, size_t bytes, int32_t max_batch
     m->W3b = (uint16_t*)(ws + l.W3b);
     m->W2t = (uint16_t*)(ws + l.W2t);
     m->W3t = (uint16_t*)(ws + l.W3t);
+    m->W2p = (uint16_t*)(ws + l.W2p);
+    m->W3p = (uint16_t*)(ws + l.W3p);
     m->norm = (float*)(ws + l.norm);
     m->partials = (float*)(ws + l.partials);
     m->lossp = (double*)(ws + l.lossp);
@@ -755,7 +776,8 @@ int lb_mlp_gradient(lb_mlp* m, const float* pre, const float* post, int32_t n, d
     if (rc != LB_OK) return rc;
     hipLaunchKernelGGL(k_mlp_update, dim3((NPARAM + TB - 1) / TB), dim3(TB), 0, m->stream, m->params, m->adam_m,
                        m->adam_v, (const float*)m->partials, n / TS, 1, 0.f, 1.f, 1.f, m->grad,
-                       (const double*)m->lossp, (double*)nullptr, 0, m->W1b, m->W2b, m->W3b, m->W2t, m->W3t);
+                       (const double*)m->lossp, (double*)nullptr, 0, m->W1b, m->W2b, m->W3b, m->W2t, m->W3t,
+                       m->W2p, m->W3p);
     rc = mcheck(m, "lb_mlp_gradient");
     if (rc != LB_OK) return rc;
     double lossp[4096];
@@ -800,7 +822,7 @@ int lb_mlp_train(lb_mlp* m, const float* pre, const float* post, int64_t n, doub
             hipLaunchKernelGGL(k_mlp_update, dim3((NPARAM + TB - 1) / TB), dim3(TB), 0, m->stream, m->params,
                                m->adam_m, m->adam_v, (const float*)m->partials, batch / TS, 0, (float)lr_t,
                                (float)bc1, (float)bc2, m->grad, (const double*)m->lossp, m->loss_epoch, e, m->W1b,
-                               m->W2b, m->W3b, m->W2t, m->W3t);
+                               m->W2b, m->W3b, m->W2t, m->W3t, m->W2p, m->W3p);
             rc = mcheck(m, "lb_mlp_train: update");
             if (rc != LB_OK) return rc;
             ++step;

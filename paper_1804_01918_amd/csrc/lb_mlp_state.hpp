@@ -23,6 +23,8 @@ struct lb_mlp {
     uint16_t* W3b;
     uint16_t* W2t;
     uint16_t* W3t;
+    uint16_t* W2p;
+    uint16_t* W3p;
     float* norm;          // [4][64]
     float* partials;      // [max_wg][NPARAM_PAD]
     double* lossp;        // [max_wg]
@@ -40,6 +42,8 @@ struct lb_mlp {
         n.W3b = W3b;
         n.W2t = W2t;
         n.W3t = W3t;
+        n.W2p = W2p;
+        n.W3p = W3p;
         n.params = params;
         n.norm = norm;
         return n;

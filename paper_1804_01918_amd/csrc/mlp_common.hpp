@@ -54,6 +54,13 @@ __device__ inline float gelu(float a)
     const float y = a * __builtin_fmaf(2.0f * GELU_C * GELU_A, a * a, 2.0f * GELU_C);
     return a / (1.0f + __expf(-y));
 }
+// The same with the hardware exponential and reciprocal (about 1 ulp each),
+// for activations that are rounded to BF16 right after.
+__device__ inline float gelu_fast(float a)
+{
+    const float y = a * __builtin_fmaf(2.0f * GELU_C * GELU_A, a * a, 2.0f * GELU_C);
+    return a * __builtin_amdgcn_rcpf(1.0f + __builtin_amdgcn_exp2f(-1.44269504088896340736f * y));
+}
 __device__ inline float gelu_grad(float a)
 {
     const float y = a * __builtin_fmaf(2.0f * GELU_C * GELU_A, a * a, 2.0f * GELU_C);
@@ -87,6 +94,23 @@ __device__ inline f32x4 mfma(bf16x8 a, bf16x8 b, f32x4 c)
     return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
 }
 
+// Register chaining of layers (inference). Computing a layer transposed,
+// H^T (hidden x sites) = W x X^T, each lane ends with 4 consecutive hidden
+// units of one site per 16-row tile; two tiles (hidden 16 apart) fill the 8
+// k-slots of the next layer's B fragment for that site. So the next layer's
+// k index runs over hidden units in the order
+//   slot 8q + j of a 32-wide k block  <->  hidden 4q + j (j < 4), 16 + 4q + j - 4 (j >= 4),
+// and its weight columns are stored permuted the same way.
+__host__ __device__ constexpr int chain_hidden(int slot)
+{
+    return (slot & ~31) + (((slot & 7) < 4) ? 4 * ((slot & 31) >> 3) + (slot & 7)
+                                             : 16 + 4 * ((slot & 31) >> 3) + (slot & 7) - 4);
+}
+__host__ __device__ constexpr int chain_slot(int hidden)
+{
+    return (hidden & ~31) + 8 * ((hidden & 15) >> 2) + (hidden & 3) + ((hidden & 16) ? 4 : 0);
+}
+
 // Device view of a network: BF16 operand copies, FP32 biases (inside the
 // packed parameters) and the standardisation of inputs and outputs.
 struct Net {
@@ -95,8 +119,12 @@ struct Net {
     const uint16_t* W3b;  // [48][128]  W3[o][h], o padded with zeros
     const uint16_t* W2t;  // [128][128] W2[h2][h1] at [h1][h2]
     const uint16_t* W3t;  // [128][64]  W3[o][h] at [h][o], o padded
+    const uint16_t* W2p;  // [128][128] W2[h2][chain_hidden(slot)] at [h2][slot]
+    const uint16_t* W3p;  // [48][128]  W3[o][chain_hidden(slot)] at [o][slot], o padded
     const float* params;  // packed FP32 parameters (biases read from here)
     const float* norm;    // [4][64]: mean z, 1/sd z, mean y, sd y
+    int ld1 = KIN;        // row strides of W1b and of W2p / W3p (the LDS copies are padded)
+    int ld23 = HID;
 };
 
 // ---- conserved part and residual of shifted populations -----------------------

@@ -10,9 +10,11 @@
 //   equilibrium values of (rho, u, T); the site falls back to the plain
 //   equilibrium when the residual exceeds the threshold or (rho, |u|, T)
 //   leaves the training box.
-// The 64 sites of a wavefront go through the network in two halves of 32
-// (two 16-row tiles), with inputs and hidden activations staged in a
-// per-wavefront LDS area; weights are read as fragments from global memory.
+// The 64 sites of a wavefront go through the network in two halves of 32.
+// Layers are computed transposed (hidden x sites) and chained in registers
+// (see chain_hidden in mlp_common.hpp); only the inputs (to bring each
+// site's 37 values into fragment order) and the outputs (to return each
+// site's 37 outputs to its lane) pass through a per-wavefront LDS area.
 #pragma once
 
 #include "mlp_common.hpp"
@@ -20,9 +22,10 @@
 namespace d2q37 {
 namespace mlp {
 
-constexpr int LDX = 72;    // row stride (elements) of the staged inputs
-constexpr int LDH = 136;   // row stride of the staged hidden activations
-constexpr int WAVE_LDS_BYTES = (32 * LDX + 32 * LDH) * 2;  // 13312
+constexpr int LDX = 80;    // row stride (bf16) of the staged inputs of a wavefront's 64 sites
+constexpr int LDH = 136;   // row stride of staged hidden activations (training)
+constexpr int LDO = 40;    // row stride (floats) of the staged outputs: same bytes as an input row
+constexpr int WAVE_LDS_BYTES = 64 * LDX * 2;  // 10240
 
 // Orders LDS traffic between the lanes of one wavefront.
 __device__ inline void wave_sync()
@@ -32,122 +35,163 @@ __device__ inline void wave_sync()
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-// Network outputs o[37] (standardised) for each lane's inputs. Every lane of
-// the wavefront must call it; inactive lanes pass any finite g.
-__device__ inline void network_outputs(const float (&g)[Q], const Net& net, uint16_t* lds, float (&o)[Q])
+__device__ inline float4 load4(const float* p) { return *(const float4*)p; }
+
+// Standardised BF16 input of population p (value g) into the lane's row.
+__device__ inline void stage_input(uint16_t* X, const Net& net, int p, float g)
 {
-    const int lane = lane_id();
-    uint16_t* X = lds;
-    uint16_t* H = lds + 32 * LDX;
-    float* O = (float*)H;
+    const float z = g * (float)(1.0 / weight(p));
+    X[lane_id() * LDX + p] = bf16_bits((z - net.norm[p]) * net.norm[64 + p]);
+}
+__device__ inline void stage_padding(uint16_t* X)
+{
+#pragma unroll
+    for (int f = Q; f < LDX; ++f) X[lane_id() * LDX + f] = 0;
+}
+
+// Network outputs of the wavefront's 64 sites. X holds the staged inputs
+// (row per site); on return the same rows hold the standardised outputs as
+// FP32, out[site * LDO + o] for o < 37. Every lane must call it.
+__device__ inline void network_outputs(const Net& net, uint16_t* X)
+{
+    const int lane = lane_id(), col = lane & 15, quad = lane >> 4;
     const float* b1 = net.params + OFF_B1;
     const float* b2 = net.params + OFF_B2;
     const float* b3 = net.params + OFF_B3;
-    const int col = lane & 15, quad = lane >> 4;
+    wave_sync();
 
+#pragma unroll 1
     for (int half = 0; half < 2; ++half) {
-        if ((lane >> 5) == half) {
-            uint16_t* row = X + (lane & 31) * LDX;
-#pragma unroll
-            for (int f = 0; f < Q; ++f) {
-                const float z = g[f] * (float)(1.0 / weight(f));
-                row[f] = bf16_bits((z - net.norm[f]) * net.norm[64 + f]);
-            }
-#pragma unroll
-            for (int f = Q; f < KIN; ++f) row[f] = 0;
-        }
-        wave_sync();
+        uint16_t* Xh = X + half * 32 * LDX;
 
-        // layer 1: [32 x 64] x [64 x 128]
-        f32x4 acc[2][8];
+        // layer 1: H1^T (128 x 32) = W1 (128 x 64) X^T (64 x 32)
+        f32x4 acc[8][2];
 #pragma unroll
-        for (int mt = 0; mt < 2; ++mt)
-#pragma unroll
-            for (int nt = 0; nt < 8; ++nt) acc[mt][nt] = f32x4{0.f, 0.f, 0.f, 0.f};
+        for (int mt = 0; mt < 8; ++mt) acc[mt][0] = acc[mt][1] = f32x4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
         for (int ks = 0; ks < 2; ++ks) {
-            const bf16x8 a0 = frag_im(X, LDX, 0, ks * 32), a1 = frag_im(X, LDX, 16, ks * 32);
+            __builtin_amdgcn_sched_barrier(0);  // one k block of weight fragments in flight
+            const bf16x8 x0 = frag_im(Xh, LDX, 0, ks * 32), x1 = frag_im(Xh, LDX, 16, ks * 32);
 #pragma unroll
-            for (int nt = 0; nt < 8; ++nt) {
-                const bf16x8 b = frag_im(net.W1b, KIN, nt * 16, ks * 32);
-                acc[0][nt] = mfma(a0, b, acc[0][nt]);
-                acc[1][nt] = mfma(a1, b, acc[1][nt]);
+            for (int mt = 0; mt < 8; ++mt) {
+                const bf16x8 a = frag_im(net.W1b, net.ld1, mt * 16, ks * 32);
+                acc[mt][0] = mfma(a, x0, acc[mt][0]);
+                acc[mt][1] = mfma(a, x1, acc[mt][1]);
             }
         }
+        __builtin_amdgcn_sched_barrier(0);
+        // bias, GELU, BF16 into the B fragments of the next layer
+        bf16x8 hb[4][2];
 #pragma unroll
-        for (int mt = 0; mt < 2; ++mt)
+        for (int kb = 0; kb < 4; ++kb) {
+            const float4 lo = load4(b1 + 32 * kb + 4 * quad), hi = load4(b1 + 32 * kb + 16 + 4 * quad);
+            const float bl[4] = {lo.x, lo.y, lo.z, lo.w}, bh[4] = {hi.x, hi.y, hi.z, hi.w};
 #pragma unroll
-            for (int nt = 0; nt < 8; ++nt) {
-                const int h = nt * 16 + col;
-                const float bias = b1[h];
+            for (int nt = 0; nt < 2; ++nt)
 #pragma unroll
-                for (int i = 0; i < 4; ++i)
-                    H[(mt * 16 + 4 * quad + i) * LDH + h] = bf16_bits(gelu(acc[mt][nt][i] + bias));
-            }
-        wave_sync();
+                for (int j = 0; j < 4; ++j) {
+                    hb[kb][nt][j] = __builtin_bit_cast(__bf16, bf16_bits(gelu_fast(acc[2 * kb][nt][j] + bl[j])));
+                    hb[kb][nt][4 + j] = __builtin_bit_cast(__bf16, bf16_bits(gelu_fast(acc[2 * kb + 1][nt][j] + bh[j])));
+                }
+        }
 
-        // layer 2: [32 x 128] x [128 x 128], in place on H
+        // layer 2: H2^T = W2 H1^T (weight columns in chained order)
 #pragma unroll
-        for (int mt = 0; mt < 2; ++mt)
+        for (int mt = 0; mt < 8; ++mt) acc[mt][0] = acc[mt][1] = f32x4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-            for (int nt = 0; nt < 8; ++nt) acc[mt][nt] = f32x4{0.f, 0.f, 0.f, 0.f};
+        for (int kb = 0; kb < 4; ++kb) {
+            __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
-        for (int ks = 0; ks < 4; ++ks) {
-            const bf16x8 a0 = frag_im(H, LDH, 0, ks * 32), a1 = frag_im(H, LDH, 16, ks * 32);
-#pragma unroll
-            for (int nt = 0; nt < 8; ++nt) {
-                const bf16x8 b = frag_im(net.W2b, HID, nt * 16, ks * 32);
-                acc[0][nt] = mfma(a0, b, acc[0][nt]);
-                acc[1][nt] = mfma(a1, b, acc[1][nt]);
+            for (int mt = 0; mt < 8; ++mt) {
+                const bf16x8 a = frag_im(net.W2p, net.ld23, mt * 16, kb * 32);
+                acc[mt][0] = mfma(a, hb[kb][0], acc[mt][0]);
+                acc[mt][1] = mfma(a, hb[kb][1], acc[mt][1]);
             }
         }
-        wave_sync();
+        __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
-        for (int mt = 0; mt < 2; ++mt)
+        for (int kb = 0; kb < 4; ++kb) {
+            const float4 lo = load4(b2 + 32 * kb + 4 * quad), hi = load4(b2 + 32 * kb + 16 + 4 * quad);
+            const float bl[4] = {lo.x, lo.y, lo.z, lo.w}, bh[4] = {hi.x, hi.y, hi.z, hi.w};
 #pragma unroll
-            for (int nt = 0; nt < 8; ++nt) {
-                const int h = nt * 16 + col;
-                const float bias = b2[h];
+            for (int nt = 0; nt < 2; ++nt)
 #pragma unroll
-                for (int i = 0; i < 4; ++i)
-                    H[(mt * 16 + 4 * quad + i) * LDH + h] = bf16_bits(gelu(acc[mt][nt][i] + bias));
-            }
-        wave_sync();
+                for (int j = 0; j < 4; ++j) {
+                    hb[kb][nt][j] = __builtin_bit_cast(__bf16, bf16_bits(gelu_fast(acc[2 * kb][nt][j] + bl[j])));
+                    hb[kb][nt][4 + j] = __builtin_bit_cast(__bf16, bf16_bits(gelu_fast(acc[2 * kb + 1][nt][j] + bh[j])));
+                }
+        }
 
-        // layer 3: [32 x 128] x [128 x 48]
-        f32x4 acc3[2][3];
+        // layer 3: O^T (48 x 32) = W3 H2^T
+        f32x4 acc3[3][2];
 #pragma unroll
-        for (int mt = 0; mt < 2; ++mt)
+        for (int mt = 0; mt < 3; ++mt) acc3[mt][0] = acc3[mt][1] = f32x4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-            for (int nt = 0; nt < 3; ++nt) acc3[mt][nt] = f32x4{0.f, 0.f, 0.f, 0.f};
+        for (int kb = 0; kb < 4; ++kb) {
+            __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
-        for (int ks = 0; ks < 4; ++ks) {
-            const bf16x8 a0 = frag_im(H, LDH, 0, ks * 32), a1 = frag_im(H, LDH, 16, ks * 32);
-#pragma unroll
-            for (int nt = 0; nt < 3; ++nt) {
-                const bf16x8 b = frag_im(net.W3b, HID, nt * 16, ks * 32);
-                acc3[0][nt] = mfma(a0, b, acc3[0][nt]);
-                acc3[1][nt] = mfma(a1, b, acc3[1][nt]);
+            for (int mt = 0; mt < 3; ++mt) {
+                const bf16x8 a = frag_im(net.W3p, net.ld23, mt * 16, kb * 32);
+                acc3[mt][0] = mfma(a, hb[kb][0], acc3[mt][0]);
+                acc3[mt][1] = mfma(a, hb[kb][1], acc3[mt][1]);
             }
         }
-        wave_sync();
+        wave_sync();  // the half's input rows are dead before its outputs overwrite them
+        float* O = (float*)Xh;
 #pragma unroll
-        for (int mt = 0; mt < 2; ++mt)
+        for (int mt = 0; mt < 3; ++mt) {
+            const int o = mt * 16 + 4 * quad;
+            if (o < LDO) {
+                float bb[4];
 #pragma unroll
-            for (int nt = 0; nt < 3; ++nt) {
-                const int oc = nt * 16 + col;
-                const float bias = oc < Q ? b3[oc] : 0.f;
+                for (int i = 0; i < 4; ++i) bb[i] = (o + i) < Q ? b3[o + i] : 0.f;
 #pragma unroll
-                for (int i = 0; i < 4; ++i) O[(mt * 16 + 4 * quad + i) * NOUT + oc] = acc3[mt][nt][i] + bias;
+                for (int nt = 0; nt < 2; ++nt) {
+                    const int site = 16 * nt + col;
+                    *(float4*)(O + site * LDO + o) = float4{acc3[mt][nt][0] + bb[0], acc3[mt][nt][1] + bb[1],
+                                                           acc3[mt][nt][2] + bb[2], acc3[mt][nt][3] + bb[3]};
+                }
             }
-        wave_sync();
-        if ((lane >> 5) == half) {
-            const float* row = O + (lane & 31) * NOUT;
-#pragma unroll
-            for (int f = 0; f < Q; ++f) o[f] = row[f];
         }
-        wave_sync();
     }
+    wave_sync();
+}
+
+// LDS copy of the inference weights, rows padded by 16 bytes so that the 16
+// rows of a fragment fall on different banks.
+constexpr int LDW1 = KIN + 8;
+constexpr int LDW23 = HID + 8;
+struct SharedWeights {
+    uint16_t W1[HID * LDW1];
+    uint16_t W2[HID * LDW23];
+    uint16_t W3[NOUT * LDW23];
+};
+
+// Copy the BF16 inference weights of `net` into LDS (all threads of the
+// workgroup; the caller synchronises) and return the view that reads them.
+template <int NTHREADS>
+__device__ inline Net share_weights(const Net& net, SharedWeights& S)
+{
+    const int tid = threadIdx.x;
+    for (int i = tid; i < HID * KIN / 8; i += NTHREADS) {
+        const int r = i / (KIN / 8), c = (i % (KIN / 8)) * 8;
+        *(uint4*)(S.W1 + r * LDW1 + c) = *(const uint4*)(net.W1b + r * KIN + c);
+    }
+    for (int i = tid; i < HID * HID / 8; i += NTHREADS) {
+        const int r = i / (HID / 8), c = (i % (HID / 8)) * 8;
+        *(uint4*)(S.W2 + r * LDW23 + c) = *(const uint4*)(net.W2p + r * HID + c);
+    }
+    for (int i = tid; i < NOUT * HID / 8; i += NTHREADS) {
+        const int r = i / (HID / 8), c = (i % (HID / 8)) * 8;
+        *(uint4*)(S.W3 + r * LDW23 + c) = *(const uint4*)(net.W3p + r * HID + c);
+    }
+    Net v = net;
+    v.W1b = S.W1;
+    v.W2p = S.W2;
+    v.W3p = S.W3;
+    v.ld1 = LDW1;
+    v.ld23 = LDW23;
+    return v;
 }
 
 struct Verdict {
@@ -155,45 +199,68 @@ struct Verdict {
     float residual;
 };
 
-// g_hat (learned, projected) and the fallback verdict of each lane's site.
-__device__ inline Verdict learned_equilibrium(const float (&g)[Q], const Net& net, uint16_t* lds, float threshold,
-                                              float (&ghat)[Q])
-{
-    float o[Q];
-    network_outputs(g, net, lds, o);
-    float d[Q];
-#pragma unroll
-    for (int f = 0; f < Q; ++f) d[f] = mulk(__builtin_fmaf(net.norm[192 + f], o[f], net.norm[128 + f]), weight(f));
-    const Conserved mg = conserved_moments(g);
-    const Conserved md = conserved_moments(d);
-    const ConservedCoef k = conserved_coef(mg.m0 - md.m0, mg.mx - md.mx, mg.my - md.my, mg.mE - md.mE);
-#pragma unroll
-    for (int f = 0; f < Q; ++f) ghat[f] = d[f] + conserved_value(f, k);
+// The learned equilibrium of a lane's site, evaluated on demand from the
+// staged network outputs: g_hat_p = d_p + P(g - d)_p, d_p = w_p (mean_y +
+// sd_y o_p).
+struct Learned {
+    const float* row;
+    ConservedCoef k;
+    Verdict verdict;
+};
 
-    // residual against the equilibrium stress and heat flux of (rho, u, T)
+__device__ inline float learned_d(const Net& net, const float* row, int p)
+{
+    return mulk(__builtin_fmaf(net.norm[192 + p], row[p], net.norm[128 + p]), weight(p));
+}
+__device__ inline float learned_value(const Learned& L, const Net& net, int p)
+{
+    return learned_d(net, L.row, p) + conserved_value(p, L.k);
+}
+
+// Projection coefficients and fallback verdict of each lane's site from its
+// populations g and the network outputs staged by network_outputs (residual
+// against the equilibrium stress and heat flux of (rho, u, T); training box
+// on rho, |u|, T).
+__device__ inline Learned learned_equilibrium(const float (&g)[Q], const Net& net, const uint16_t* X, float threshold)
+{
+    Learned L;
+    L.row = (const float*)X + lane_id() * LDO;
+    float d0 = 0.f, dx = 0.f, dy = 0.f, de = 0.f;
+#pragma unroll
+    for (int p = 0; p < Q; ++p) {
+        const float d = learned_d(net, L.row, p);
+        d0 += d;
+        if (CX[p] != 0) dx = __builtin_fmaf((float)CX[p], d, dx);
+        if (CY[p] != 0) dy = __builtin_fmaf((float)CY[p], d, dy);
+        if (c2_of(p) != 0) de = __builtin_fmaf((float)c2_of(p), d, de);
+    }
+    const Conserved mg = conserved_moments(g);
+    const float md0 = d0, mdx = mulk(dx, R), mdy = mulk(dy, R), mdE = mulk(de, R2) - 2.0f * d0;
+    L.k = conserved_coef(mg.m0 - md0, mg.mx - mdx, mg.my - mdy, mg.mE - mdE);
+
     const float rho = 1.0f + mg.m0;
     const float ux = mg.mx / rho, uy = mg.my / rho;
     const float u2 = ux * ux + uy * uy;
     const float T = 1.0f + (mg.mE - rho * u2) / (2.0f * rho);
     float sxy = 0.f, snn = 0.f, sqx = 0.f, sqy = 0.f;  // lattice units
 #pragma unroll
-    for (int f = 0; f < Q; ++f) {
-        if (CX[f] * CY[f] != 0) sxy = __builtin_fmaf((float)(CX[f] * CY[f]), ghat[f], sxy);
-        if (CX[f] * CX[f] - CY[f] * CY[f] != 0)
-            snn = __builtin_fmaf((float)(CX[f] * CX[f] - CY[f] * CY[f]), ghat[f], snn);
-        if (CX[f] != 0) sqx = __builtin_fmaf((float)(CX[f] * c2_of(f)), ghat[f], sqx);
-        if (CY[f] != 0) sqy = __builtin_fmaf((float)(CY[f] * c2_of(f)), ghat[f], sqy);
+    for (int p = 0; p < Q; ++p) {
+        const float gh = learned_value(L, net, p);
+        if (CX[p] * CY[p] != 0) sxy = __builtin_fmaf((float)(CX[p] * CY[p]), gh, sxy);
+        if (CX[p] * CX[p] - CY[p] * CY[p] != 0)
+            snn = __builtin_fmaf((float)(CX[p] * CX[p] - CY[p] * CY[p]), gh, snn);
+        if (CX[p] != 0) sqx = __builtin_fmaf((float)(CX[p] * c2_of(p)), gh, sqx);
+        if (CY[p] != 0) sqy = __builtin_fmaf((float)(CY[p] * c2_of(p)), gh, sqy);
     }
     const float q4 = u2 + 4.0f * T;
     const float r1 = fabsf(mulk(sxy, R2) - rho * ux * uy);
     const float r2 = fabsf(mulk(snn, R2) - rho * (ux * ux - uy * uy));
     const float r3 = fabsf(mulk(sqx, R * R2) - rho * ux * q4);
     const float r4 = fabsf(mulk(sqy, R * R2) - rho * uy * q4);
-    Verdict v;
-    v.residual = fmaxf(fmaxf(r1, r2), fmaxf(r3, r4));
+    L.verdict.residual = fmaxf(fmaxf(r1, r2), fmaxf(r3, r4));
     const bool in_box = rho >= 0.9f && rho <= 1.1f && u2 <= 0.01f && T >= 0.9f && T <= 1.1f;
-    v.fallback = !in_box || !(v.residual <= threshold);
-    return v;
+    L.verdict.fallback = !in_box || !(L.verdict.residual <= threshold);
+    return L;
 }
 
 }  // namespace mlp

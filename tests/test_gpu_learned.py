@@ -1,0 +1,290 @@
+"""GPU parity of the learned collide against its oracle (oracle/surrogate.py).
+
+Every network used here is created by the oracle (its own Philox init, its
+own training) and handed to the GPU; GPU-trained networks are judged only by
+the plain collide (fallback statistics, error against the FP64 run).
+
+Tolerances:
+* pairs: FP32 evaluation of the equilibrium and of the Box-Muller draws,
+  |pre_gpu - pre_oracle| / w_p <= 4e-6;
+* network parameters after init: bit-exact;
+* gradient: per parameter block relative L2 <= 2e-3 and cosine >= 0.9999;
+  the kernels and the BF16-emulating oracle round at the same points, so the
+  residue is FP32 versus FP64 accumulation plus rare BF16 ties that round the
+  other way;
+* learned equilibrium: |g_hat_gpu - g_hat_oracle| / w_p <= 2e-3 (the same
+  BF16 ties, each worth 2^-8 of an activation), and the conserved moments of
+  g_hat equal those of the input to FP32 rounding.
+"""
+import numpy as np
+import pytest
+
+from oracle import lbm, surrogate as S
+from oracle.lattice import constants
+from paper_1804_01918_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+from paper_1804_01918_amd import lb  # noqa: E402
+
+TAU = 0.8
+
+
+def _f32(a):
+    return np.ascontiguousarray(a, dtype=np.float32).astype(np.float64)
+
+
+def _dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float32)).cuda()
+
+
+@pytest.fixture(scope="module")
+def oracle_net():
+    """A network trained by the oracle on its own pairs (FP32-rounded)."""
+    pre, post = S.make_pairs(4096, seed=21, tau=TAU)
+    pre, post = _f32(pre), _f32(post)
+    norm = S.fit_normalization(pre, post, TAU)
+    theta, losses = S.train(pre, post, TAU, S.init_params(4), norm, batch=256, epochs=6, lr0=3e-3, seed=8)
+    return _f32(theta), _f32(norm), losses
+
+
+def _gpu_net(theta, norm, max_batch=8192):
+    m = lb.Mlp(max_batch)
+    m.set_params(theta)
+    m.set_normalization(norm)
+    return m
+
+
+def test_pairgen_matches_oracle(consts):
+    pre, post = lb.pairgen(4096, 7, TAU)
+    opre, opost = S.make_pairs(4096, 7, TAU)
+    w = consts["w"]
+    assert np.max(np.abs(pre.cpu().numpy() - opre) / w) <= 4e-6
+    assert np.max(np.abs(post.cpu().numpy() - opost) / w) <= 4e-6
+
+
+def test_pairgen_offsets_are_counter_based(consts):
+    a, _ = lb.pairgen(300, 5, TAU)
+    b, _ = S.make_pairs(100, 5, TAU, start=200)
+    assert np.max(np.abs(a[200:].cpu().numpy() - b) / consts["w"]) <= 4e-6
+
+
+def test_init_bitwise():
+    m = lb.Mlp(256)
+    m.init(1)
+    assert np.array_equal(m.get_params(), S.init_params(1).astype(np.float32))
+    m.init(2 ** 40 + 3)
+    assert np.array_equal(m.get_params(), S.init_params(2 ** 40 + 3).astype(np.float32))
+
+
+def test_params_and_normalization_roundtrip(oracle_net):
+    theta, norm, _ = oracle_net
+    m = _gpu_net(theta, norm)
+    assert np.array_equal(m.get_params(), theta.astype(np.float32))
+    assert np.allclose(m.get_normalization(), norm, rtol=1e-6, atol=0)
+
+
+def test_fit_normalization_matches_oracle():
+    pre, post = S.make_pairs(2048, seed=3, tau=TAU)
+    pre, post = _f32(pre), _f32(post)
+    m = lb.Mlp(256)
+    m.fit_normalization(_dev(pre), _dev(post), TAU)
+    got = m.get_normalization()
+    want = S.fit_normalization(pre, post, TAU)
+    scale = np.stack([want[1], want[1], want[3], want[3]])
+    assert np.max(np.abs(got - want) / scale) < 1e-4
+
+
+@pytest.mark.parametrize("n", [32, 256])
+def test_gradient_matches_oracle(n):
+    rng = np.random.default_rng(n)
+    pre, post = S.make_pairs(n, seed=3, tau=TAU)
+    pre, post = _f32(pre), _f32(post)
+    norm = _f32(S.fit_normalization(pre, post, TAU))
+    theta = _f32(S.init_params(1) + 0.02 * rng.standard_normal(S.NPARAM))
+    m = _gpu_net(theta, norm)
+    nf = m.get_normalization().astype(np.float64)
+    g_gpu, loss_gpu = m.gradient(_dev(pre), _dev(post), TAU)
+    z, y = S.features(pre, post, TAU)
+    loss, g = S.loss_and_grad(theta, (z - nf[0]) / nf[1], (y - nf[2]) / nf[3], emulate=True)
+    assert abs(loss_gpu / loss - 1) < 1e-5
+    k = 0
+    for name, shape in S.SHAPES:
+        cnt = int(np.prod(shape))
+        a, b = g_gpu[k:k + cnt].astype(np.float64), g[k:k + cnt]
+        k += cnt
+        assert np.linalg.norm(a - b) <= 2e-3 * np.linalg.norm(b), name
+        assert a @ b >= 0.9999 * np.linalg.norm(a) * np.linalg.norm(b), name
+
+
+def test_training_steps_match_oracle(oracle_net):
+    """Two Adam steps (batch 128 of 256 pairs, the epoch order of the seed):
+    the loss of the steps and the parameters agree with the oracle's."""
+    pre, post = S.make_pairs(256, seed=12, tau=TAU)
+    pre, post = _f32(pre), _f32(post)
+    norm = _f32(S.fit_normalization(pre, post, TAU))
+    theta0 = _f32(S.init_params(9))
+    m = _gpu_net(theta0, norm, max_batch=256)
+    nf = m.get_normalization().astype(np.float64)
+    lr = 1e-3
+    losses = m.train(_dev(pre), _dev(post), TAU, batch=128, epochs=1, lr=lr, seed=77)
+    theta_gpu = m.get_params().astype(np.float64)
+    theta_orc, ol = S.train(pre, post, TAU, theta0, nf, batch=128, epochs=1, lr0=lr, seed=77)
+    assert abs(losses[0] / np.mean(ol) - 1) < 1e-4
+    # Adam moves each parameter by about lr per step; gradients that differ in
+    # sign between the two sides (entries near zero) move it the other way.
+    d = np.abs(theta_gpu - theta_orc)
+    assert np.quantile(d, 0.99) <= 0.05 * lr
+    assert d.max() <= 4 * lr
+
+
+def test_learned_equilibrium_matches_oracle(consts, oracle_net):
+    theta, norm, _ = oracle_net
+    m = _gpu_net(theta, norm)
+    nf = m.get_normalization().astype(np.float64)
+    pre, _ = S.make_pairs(2048, seed=31, tau=TAU)
+    pre = _f32(pre)
+    gh, res, fb = m.equilibrium(_dev(pre), 1e9)
+    gh = gh.cpu().numpy()
+    want = S.surrogate_equilibrium(pre, theta, nf, emulate=True)
+    w = consts["w"]
+    rho, ux, uy, T = S.macro(pre)
+    # perturbed pairs slightly outside the training box take the plain
+    # equilibrium (compare those where the box test is not a rounding tie)
+    box = S.in_box(rho, ux, uy, T)
+    assert np.array_equal(fb.cpu().numpy().astype(bool), ~box)
+    exact = lbm.init(rho[:, None], ux[:, None], uy[:, None], T[:, None])[:, :, 0].T - w
+    want = np.where(box[:, None], want, exact)
+    assert np.max(np.abs(gh - want) / w) <= 2e-3
+    # projection: conserved moments of g_hat are those of the input
+    for phi in S._basis():
+        scale = np.abs(pre * phi).sum(1) + 1e-3
+        assert np.max(np.abs(gh @ phi - pre @ phi) / scale) < 1e-5
+    # residual and verdict agree with the oracle away from the threshold
+    r_orc = S.residual(S.surrogate_equilibrium(pre, theta, nf, emulate=True), rho, ux, uy, T)
+    assert np.max(np.abs(res.cpu().numpy() - r_orc)) < 1e-5 + 1e-2 * r_orc.max()
+    thr = float(np.median(r_orc))
+    _, _, fb2 = m.equilibrium(_dev(pre), thr)
+    fb2 = fb2.cpu().numpy().astype(bool)
+    away = np.abs(r_orc - thr) > 0.05 * thr
+    assert np.array_equal(fb2[away], ((r_orc > thr) | ~box)[away])
+
+
+def test_out_of_box_sites_fall_back(oracle_net):
+    theta, norm, _ = oracle_net
+    m = _gpu_net(theta, norm)
+    w = constants()["w"]
+    hot = lbm.init(np.full((8, 1), 1.0), np.zeros((8, 1)), np.zeros((8, 1)), np.full((8, 1), 1.3))[:, :, 0].T - w
+    gh, _, fb = m.equilibrium(_dev(hot), 1e9)
+    assert fb.cpu().numpy().all()
+    # the fallback is the plain equilibrium
+    assert np.max(np.abs(gh.cpu().numpy() - hot) / w) < 1e-5
+
+
+@pytest.mark.parametrize("kind", ["shear_wave", "rayleigh_taylor"])
+def test_learned_step_matches_oracle(consts, oracle_net, kind):
+    theta, norm, _ = oracle_net
+    m = _gpu_net(theta, norm)
+    nf = m.get_normalization().astype(np.float64)
+    lx, ly = 64, 128
+    fields = inputs.make_state(kind, lx, ly, seed=2)
+    sites = [(0, 0), (lx - 1, ly - 1), (5, 64), (33, 7), (17, 100), (60, 3)]
+    with lb.Lattice(lx, ly, TAU, fields, precision="f32s", layout="caosoa") as lat:
+        lat.set_surrogate(m, 1e9)
+        lat.step(1)
+        f = lat.get_populations().cpu().numpy()
+        nfb, ntot = lat.surrogate_counts()
+    assert ntot == lx * ly
+    got = np.stack([f[:, x, y] for x, y in sites])
+    w = consts["w"]
+
+    def collide(win):
+        g = _f32(win.reshape(37, -1).T - w)
+        out, _, _ = S.surrogate_collide(g, TAU, theta, nf, 1e9)
+        return (out + w).T.reshape(win.shape)
+
+    ref = np.stack([_window_step(fields, s, collide) for s in sites])
+    assert np.max(np.abs(got - ref) / w) <= 2e-3 / TAU
+
+
+def _window_step(fields, site, collide):
+    """One step at `site` on its 7 x 7 dependency window with a given collide."""
+    rho, ux, uy, T = fields
+    lx, ly = rho.shape
+    x0, y0 = site
+    xs, ys = (x0 + np.arange(-3, 4)) % lx, (y0 + np.arange(-3, 4)) % ly
+    ix = np.ix_(xs, ys)
+    win = lbm.init(rho[ix], ux[ix], uy[ix], T[ix])
+    w = constants()["w"][:, None, None]
+    win = w + _f32(win - w)   # the lattice stores FP32 deviations
+    c = constants()["c"]
+    new = np.empty((37, 1, 1))
+    for p, (cx, cy) in enumerate(c):
+        new[p, 0, 0] = win[p, 3 - cx, 3 - cy]
+    return collide(new)[:, 0, 0]
+
+
+def test_threshold_zero_is_the_plain_step(oracle_net):
+    """With threshold 0 every site falls back to the plain FP32 collide: the
+    learned step is then bit-identical to the plain step."""
+    theta, norm, _ = oracle_net
+    m = _gpu_net(theta, norm)
+    fields = inputs.shear_wave(32, 64, seed=3)
+    outs = []
+    for learned in (True, False):
+        with lb.Lattice(32, 64, TAU, fields, precision="f32s", layout="soa") as lat:
+            if learned:
+                lat.set_surrogate(m, 0.0)
+            lat.step(5)
+            outs.append(lat.get_populations().cpu().numpy())
+            if learned:
+                assert lat.surrogate_counts() == (5 * 32 * 64, 5 * 32 * 64)
+    assert np.array_equal(outs[0], outs[1])
+
+
+@pytest.mark.parametrize("layout", ["soa", "caosoa"])
+def test_learned_fused_equals_split(oracle_net, layout):
+    theta, norm, _ = oracle_net
+    m = _gpu_net(theta, norm)
+    fields = inputs.rayleigh_taylor(24, 64, seed=1)
+    outs = []
+    for fused in (True, False):
+        with lb.Lattice(24, 64, TAU, fields, precision="f32s", layout=layout) as lat:
+            lat.set_surrogate(m, 1e-3)
+            if fused:
+                lat.step(4)
+            else:
+                for _ in range(4):
+                    lat.propagate()
+                    lat.collide()
+            outs.append(lat.get_populations().cpu().numpy())
+    assert np.array_equal(outs[0], outs[1])
+
+
+def test_learned_conserves_mass_momentum_energy(consts, oracle_net):
+    theta, norm, _ = oracle_net
+    m = _gpu_net(theta, norm)
+    lx, ly, n = 64, 128, 100
+    fields = inputs.shear_wave(lx, ly, seed=2)
+    f0 = lbm.init(*fields)
+    g = np.abs(f0 - consts["w"][:, None, None])
+    xi = consts["xi"]
+    scale = np.array([g.sum(), (g * np.abs(xi[:, 0])[:, None, None]).sum(),
+                      (g * np.abs(xi[:, 1])[:, None, None]).sum(),
+                      (g * 0.5 * (xi ** 2).sum(1)[:, None, None]).sum()])
+    with lb.Lattice(lx, ly, TAU, fields, precision="f32s", layout="soa") as lat:
+        lat.set_surrogate(m, 1e-3)
+        a0 = lat.audit()
+        lat.step(n)
+        a1 = lat.audit()
+    assert np.all(np.abs(a1 - a0) <= n * 2.0 ** -24 * scale * 8), (a1 - a0)
+
+
+def test_set_surrogate_rejects_other_precisions(oracle_net):
+    theta, norm, _ = oracle_net
+    m = _gpu_net(theta, norm)
+    with lb.Lattice(8, 64, TAU, inputs.random_equilibrium(8, 64), precision="f64") as lat:
+        with pytest.raises(lb.LBError) as e:
+            lat.set_surrogate(m, 1e-3)
+        assert e.value.code == lb.LB_EUNSUPPORTED
