@@ -8,9 +8,12 @@ over K timed steps with the state resident in HBM.
 
 The same line carries the other forms of the step measured on the same GPU
 (FP32-shifted and FP16-shifted storage with their per-field error against
-the FP64 run, the AoS/CSoA/CAoSoA layouts, the split propagate + collide
-path), a roofline object for the dominant kernel and the CPU oracle timed on
-the host cores.
+the FP64 run on the shear wave and on a thermal Rayleigh-Taylor-like state,
+the AoS/SoA/CSoA layouts, the split propagate + collide path, the learned
+collide trained on the GPU from 10M pairs, and the 8192 x 8192
+Rayleigh-Taylor-like lattice in FP64, FP32-shifted and learned form), a
+roofline object for the dominant kernel and the CPU oracle timed on the host
+cores.
 """
 from __future__ import annotations
 
@@ -30,6 +33,14 @@ sys.path.insert(0, ROOT)
 METRIC = "MLUPS fused step, FP64 vs FP32-shifted/surrogate at stated err; % HBM roof"
 LX = LY = 2048
 TAU = 0.8
+# Learned collide: training set and schedule, fallback threshold.
+NPAIRS = 10_000_000
+PAIR_SEED, INIT_SEED, ORDER_SEED = 11, 5, 17
+EPOCHS, BATCH, LR = 32, 8192, 3e-3
+THRESHOLD = 5e-5
+# MFMA work of one site (37-128-128-37, multiply-adds counted as 2 flops).
+MLP_FLOP_PER_SITE = 2 * (37 * 128 + 128 * 128 + 128 * 37)
+BF16_PEAK_TFLOPS = 2500.0
 PROFILE_TRAFFIC = os.path.join(ROOT, "profiles", "traffic.json")
 
 
@@ -120,6 +131,67 @@ def cpu_baseline(seconds_target: float = 12.0):
             "sample": f"FP64 oracle, {lx}x{ly} shear-wave lattice, {steps} steps, 1 thread, {dt:.1f} s"}
 
 
+def learned_variant(args, torch, lb, inputs, run, counts, nsites, shear_ref, rt_ref):
+    """Train the network on the GPU (pairs, standardisation, Adam), then time
+    the learned fused step on the shear wave and state its error against the
+    FP64 run of the same number of steps."""
+    from paper_1804_01918_amd.roofline import HBM_PEAK_GBS, bytes_per_site
+    t0 = time.perf_counter()
+    pre, post = lb.pairgen(NPAIRS, PAIR_SEED, TAU)
+    torch.cuda.synchronize()
+    t_pairs = time.perf_counter() - t0
+    net = lb.Mlp(BATCH)
+    net.fit_normalization(pre, post, TAU)
+    net.init(INIT_SEED)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    losses = net.train(pre, post, TAU, BATCH, EPOCHS, LR, ORDER_SEED)
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t0
+    del pre, post
+    torch.cuda.empty_cache()
+    counts.clear()
+    dt, mom = run("f32s", "caosoa", args.steps, args.warmup, keep=True, net=net)
+    m = nsites * args.steps / dt / 1e6
+    v = {"mlups": m, "ms_per_step": dt / args.steps * 1e3, "threshold": THRESHOLD,
+         "fallback_fraction": counts.get("fallback_fraction"),
+         "mfma_tflops": m * 1e6 * MLP_FLOP_PER_SITE / 1e12,
+         "mfma_frac": m * 1e6 * MLP_FLOP_PER_SITE / 1e12 / BF16_PEAK_TFLOPS,
+         "hbm_frac": m * 1e6 * bytes_per_site("f32") / (HBM_PEAK_GBS * 1e9),
+         "error_vs_f64_after_steps": args.steps + args.warmup,
+         "field_error_vs_f64": field_errors(shear_ref, mom) if shear_ref is not None else None,
+         "training": {"pairs": NPAIRS, "pairgen_s": t_pairs, "epochs": EPOCHS, "batch": BATCH, "lr": LR,
+                      "adam_steps": (NPAIRS // BATCH) * EPOCHS, "train_s": t_train,
+                      "loss_first_epoch": float(losses[0]), "loss_last_epoch": float(losses[-1])}}
+    if rt_ref is not None:
+        rt = (LX, LY, [torch.from_numpy(a).cuda() for a in inputs.rayleigh_taylor(LX, LY, seed=0)])
+        counts.clear()
+        _, mom = run("f32s", "caosoa", args.steps, args.warmup, keep=True, state=rt, net=net)
+        v["rayleigh_taylor_2048"] = {"fallback_fraction": counts.get("fallback_fraction"),
+                                     "field_error_vs_f64": field_errors(rt_ref, mom)}
+    return v, net
+
+
+def scale_variant(args, torch, inputs, run, counts, net):
+    """8192 x 8192 Rayleigh-Taylor-like lattice: FP64, FP32-shifted and the
+    learned collide on the same GPU, errors against the FP64 run."""
+    n = 8192
+    state = (n, n, [torch.from_numpy(a).cuda() for a in inputs.rayleigh_taylor(n, n, seed=0)])
+    steps, warm = args.scale_steps, args.warmup
+    out = {"lattice": [n, n], "steps": steps + warm, "timed_steps": steps}
+    dt, ref = run("f64", "caosoa", steps, warm, keep=True, state=state)
+    out["f64"] = {"mlups": n * n * steps / dt / 1e6}
+    dt, mom = run("f32s", "caosoa", steps, warm, keep=True, state=state)
+    out["f32s"] = {"mlups": n * n * steps / dt / 1e6, "field_error_vs_f64": field_errors(ref, mom)}
+    counts.clear()
+    dt, mom = run("f32s", "caosoa", steps, warm, keep=True, state=state, net=net)
+    out["learned_f32s"] = {"mlups": n * n * steps / dt / 1e6, "fallback_fraction": counts.get("fallback_fraction"),
+                           "field_error_vs_f64": field_errors(ref, mom)}
+    del state, ref, mom
+    torch.cuda.empty_cache()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -128,6 +200,9 @@ def main():
     ap.add_argument("--variant-steps", type=int, default=200)
     ap.add_argument("--no-variants", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-learned", action="store_true")
+    ap.add_argument("--no-scale", action="store_true")
+    ap.add_argument("--scale-steps", type=int, default=500)
     ap.add_argument("--only", default=None, help="precision:layout[:split] to time alone")
     ap.add_argument("--copy-bytes", type=int, default=0,
                     help="only run the library's copy kernel on buffers of this size (counter calibration)")
@@ -149,9 +224,13 @@ def main():
         return
     fields = [torch.from_numpy(a).cuda() for a in inputs.shear_wave(LX, LY, seed=0)]
     nsites = LX * LY
+    counts = {}
 
-    def run(prec, layout, steps, warmup, split=False, keep=False):
-        lat = lb.Lattice(LX, LY, TAU, fields, precision=prec, layout=layout, audit=True)
+    def run(prec, layout, steps, warmup, split=False, keep=False, state=None, net=None, threshold=THRESHOLD):
+        lx, ly, flds = state if state is not None else (LX, LY, fields)
+        lat = lb.Lattice(lx, ly, TAU, flds, precision=prec, layout=layout, audit=True)
+        if net is not None:
+            lat.set_surrogate(net, threshold)
         if split:
             for _ in range(warmup):
                 lat.propagate()
@@ -160,6 +239,9 @@ def main():
             lat.step(warmup)
         dt = timed_steps(lat, torch, steps, split=split)
         mom = lat.moments() if keep else None
+        if net is not None:
+            fb, tot = lat.surrogate_counts()
+            counts["fallback_fraction"] = fb / max(tot, 1)
         lat.close()
         del lat
         torch.cuda.empty_cache()
@@ -217,7 +299,26 @@ def main():
         cb = copy_bandwidth(torch, lb, alg_bytes // 2)
         variants["copy_kernel_gbs"] = cb
         out["roofline"]["frac_of_copy"] = achieved / cb
+
+        # Precision on the thermal Rayleigh-Taylor-like state.
+        rt = (LX, LY, [torch.from_numpy(a).cuda() for a in inputs.rayleigh_taylor(LX, LY, seed=0)])
+        nrt = args.steps + args.warmup
+        _, rt_ref = run("f64", "caosoa", args.steps, args.warmup, keep=True, state=rt)
+        variants["rayleigh_taylor_2048"] = {"steps": nrt}
+        for prec in ("f32s", "f16s"):
+            _, mom = run(prec, "caosoa", args.steps, args.warmup, keep=True, state=rt)
+            variants["rayleigh_taylor_2048"][f"{prec}_field_error_vs_f64"] = field_errors(rt_ref, mom)
         out["variants"] = variants
+
+    if not args.no_learned:
+        out["variants"] = out.get("variants", {})
+        lv, net = learned_variant(args, torch, lb, inputs, run, counts, nsites, ref_mom, rt_ref if not args.no_variants else None)
+        lv["mlups_vs_f32s_plain"] = (lv["mlups"] / out["variants"]["f32s_caosoa_fused"]["mlups"]
+                                     if "f32s_caosoa_fused" in out["variants"] else None)
+        out["variants"]["learned_f32s_caosoa_fused"] = lv
+        if not args.no_scale:
+            out["variants"]["scale_8192_rayleigh_taylor"] = scale_variant(args, torch, inputs, run, counts, net)
+        net.close()
 
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline()

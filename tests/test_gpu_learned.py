@@ -288,3 +288,61 @@ def test_set_surrogate_rejects_other_precisions(oracle_net):
         with pytest.raises(lb.LBError) as e:
             lat.set_surrogate(m, 1e-3)
         assert e.value.code == lb.LB_EUNSUPPORTED
+
+
+def test_trained_network_gain(consts):
+    """What training buys: the same network before and after GPU training
+    (Adam on GPU-drawn pairs), judged only by the exact equilibrium and the
+    plain FP64 step.
+    * Held-out pairs: the trained network's equilibrium error is at least
+      ten times smaller; at residual threshold 1e-3 at most 5 % of the pairs
+      fall back, where the untrained network sends at least 90 % to the
+      plain collide.
+    * A 1024 x 1024 shear wave, 1000 steps, threshold 1e-4: the trained
+      network collides at least 99 % of the site updates itself and stays
+      within 3e-4 of the FP64 run in every field; the untrained network
+      passes the residual test at fewer than 10 % of them."""
+    w = consts["w"]
+    pre, post = lb.pairgen(1 << 20, 31, TAU)
+    trained, untrained = lb.Mlp(8192), lb.Mlp(8192)
+    for m in (trained, untrained):
+        m.fit_normalization(pre, post, TAU)
+        m.init(5)
+    losses = trained.train(pre, post, TAU, 8192, 32, 3e-3, 17)
+    assert losses[-1] < losses[0] / 100
+
+    vpre, vpost = lb.pairgen(1 << 16, 77, TAU)
+    geq = (vpre + TAU * (vpost - vpre)).double().cpu().numpy()
+    wd = np.asarray(w)
+    stats = {}
+    for name, m in (("trained", trained), ("untrained", untrained)):
+        ghat, res, _ = m.equilibrium(vpre, 1e30)
+        err = np.abs(ghat.double().cpu().numpy() - geq) / wd
+        _, _, fb = m.equilibrium(vpre, 1e-3)
+        stats[name] = (float(np.median(err)), float(fb.float().mean()))
+    print("held-out median error / fallback fraction:", stats)
+    assert stats["trained"][0] * 10 <= stats["untrained"][0]
+    assert stats["untrained"][1] >= 0.9
+    assert stats["trained"][1] <= 0.05
+
+    lx, ly, nsteps = 1024, 1024, 1000
+    fields = [torch.from_numpy(a).cuda() for a in inputs.shear_wave(lx, ly, seed=3)]
+    ref = lb.Lattice(lx, ly, TAU, fields, precision="f64")
+    ref.step(nsteps)
+    rm = ref.moments()
+    ref.close()
+    out = {}
+    for name, m in (("trained", trained), ("untrained", untrained)):
+        lat = lb.Lattice(lx, ly, TAU, fields, precision="f32s")
+        lat.set_surrogate(m, 1e-4)
+        lat.step(nsteps)
+        mm = lat.moments()
+        nfb, ntot = lat.surrogate_counts()
+        lat.close()
+        out[name] = (nfb / ntot, max(float((b - a).abs().max()) for a, b in zip(rm, mm)))
+    print("lattice fallback fraction / max field error after", nsteps, "steps:", out)
+    assert out["trained"][0] <= 0.01
+    assert out["trained"][1] <= 3e-4
+    assert out["untrained"][0] >= 0.9
+    trained.close()
+    untrained.close()
