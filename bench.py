@@ -18,8 +18,6 @@ cores.
 from __future__ import annotations
 
 import argparse
-import glob
-import hashlib
 import json
 import os
 import sys
@@ -42,15 +40,6 @@ THRESHOLD = 5e-5
 MLP_FLOP_PER_SITE = 2 * (37 * 128 + 128 * 128 + 128 * 37)
 BF16_PEAK_TFLOPS = 2500.0
 PROFILE_TRAFFIC = os.path.join(ROOT, "profiles", "traffic.json")
-
-
-def source_digest() -> str:
-    h = hashlib.sha256()
-    for path in sorted(glob.glob(os.path.join(ROOT, "paper_1804_01918_amd", "csrc", "*"))):
-        with open(path, "rb") as fh:
-            h.update(os.path.basename(path).encode())
-            h.update(fh.read())
-    return h.hexdigest()[:16]
 
 
 def timed_steps(lat, torch, nsteps: int, split: bool = False) -> float:
@@ -101,14 +90,15 @@ def copy_bandwidth(torch, lb, nbytes: int, reps: int = 20) -> float:
 def traffic_entry(kernel: str, per_launch_sites: int):
     """HBM bytes per launch from the committed rocprofv3 counter summary, if
     it was taken on the current kernel sources; else None."""
+    from paper_1804_01918_amd.profsummary import source_digest
     if not os.path.exists(PROFILE_TRAFFIC):
         return None
     with open(PROFILE_TRAFFIC) as fh:
         rec = json.load(fh)
-    if rec.get("source_digest") != source_digest():
-        return None
     k = rec.get("kernels", {}).get(kernel)
-    if not k or k.get("sites") != per_launch_sites:
+    if not k or k.get("sites") != per_launch_sites or "source_files" not in k:
+        return None
+    if k.get("source_digest") != source_digest(k["source_files"]):
         return None
     return k.get("hbm_bytes_per_launch")
 
@@ -131,11 +121,10 @@ def cpu_baseline(seconds_target: float = 12.0):
             "sample": f"FP64 oracle, {lx}x{ly} shear-wave lattice, {steps} steps, 1 thread, {dt:.1f} s"}
 
 
-def learned_variant(args, torch, lb, inputs, run, counts, nsites, shear_ref, rt_ref):
-    """Train the network on the GPU (pairs, standardisation, Adam), then time
-    the learned fused step on the shear wave and state its error against the
-    FP64 run of the same number of steps."""
-    from paper_1804_01918_amd.roofline import HBM_PEAK_GBS, bytes_per_site
+def train_network(torch, lb, train: bool = True):
+    """Pairs from the plain FP32 collide, standardisation, Philox init and
+    Adam, all on the GPU; returns the network and the training record. With
+    train=False the network keeps its initial weights."""
     t0 = time.perf_counter()
     pre, post = lb.pairgen(NPAIRS, PAIR_SEED, TAU)
     torch.cuda.synchronize()
@@ -145,11 +134,22 @@ def learned_variant(args, torch, lb, inputs, run, counts, nsites, shear_ref, rt_
     net.init(INIT_SEED)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    losses = net.train(pre, post, TAU, BATCH, EPOCHS, LR, ORDER_SEED)
+    losses = net.train(pre, post, TAU, BATCH, EPOCHS, LR, ORDER_SEED) if train else [float("nan")]
     torch.cuda.synchronize()
     t_train = time.perf_counter() - t0
     del pre, post
     torch.cuda.empty_cache()
+    return net, {"pairs": NPAIRS, "pairgen_s": t_pairs, "epochs": EPOCHS, "batch": BATCH, "lr": LR,
+                 "adam_steps": (NPAIRS // BATCH) * EPOCHS, "train_s": t_train,
+                 "loss_first_epoch": float(losses[0]), "loss_last_epoch": float(losses[-1])}
+
+
+def learned_variant(args, torch, lb, inputs, run, counts, nsites, shear_ref, rt_ref):
+    """Train the network on the GPU (pairs, standardisation, Adam), then time
+    the learned fused step on the shear wave and state its error against the
+    FP64 run of the same number of steps."""
+    from paper_1804_01918_amd.roofline import HBM_PEAK_GBS, bytes_per_site
+    net, training = train_network(torch, lb)
     counts.clear()
     dt, mom = run("f32s", "caosoa", args.steps, args.warmup, keep=True, net=net)
     m = nsites * args.steps / dt / 1e6
@@ -158,11 +158,11 @@ def learned_variant(args, torch, lb, inputs, run, counts, nsites, shear_ref, rt_
          "mfma_tflops": m * 1e6 * MLP_FLOP_PER_SITE / 1e12,
          "mfma_frac": m * 1e6 * MLP_FLOP_PER_SITE / 1e12 / BF16_PEAK_TFLOPS,
          "hbm_frac": m * 1e6 * bytes_per_site("f32") / (HBM_PEAK_GBS * 1e9),
+         "hbm_traffic_bytes_per_launch": traffic_entry("k_step_learned_f32s_caosoa_2048x2048", nsites),
+         "algorithmic_bytes_per_launch": bytes_per_site("f32") * nsites,
          "error_vs_f64_after_steps": args.steps + args.warmup,
          "field_error_vs_f64": field_errors(shear_ref, mom) if shear_ref is not None else None,
-         "training": {"pairs": NPAIRS, "pairgen_s": t_pairs, "epochs": EPOCHS, "batch": BATCH, "lr": LR,
-                      "adam_steps": (NPAIRS // BATCH) * EPOCHS, "train_s": t_train,
-                      "loss_first_epoch": float(losses[0]), "loss_last_epoch": float(losses[-1])}}
+         "training": training}
     if rt_ref is not None:
         rt = (LX, LY, [torch.from_numpy(a).cuda() for a in inputs.rayleigh_taylor(LX, LY, seed=0)])
         counts.clear()
@@ -201,9 +201,11 @@ def main():
     ap.add_argument("--no-variants", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-learned", action="store_true")
+    ap.add_argument("--untrained", action="store_true",
+                    help="with --only learned: skip the training (counter runs; HBM bytes do not depend on it)")
     ap.add_argument("--no-scale", action="store_true")
     ap.add_argument("--scale-steps", type=int, default=500)
-    ap.add_argument("--only", default=None, help="precision:layout[:split] to time alone")
+    ap.add_argument("--only", default=None, help="precision:layout[:split], or 'learned', to time alone")
     ap.add_argument("--copy-bytes", type=int, default=0,
                     help="only run the library's copy kernel on buffers of this size (counter calibration)")
     ap.add_argument("--copy-reps", type=int, default=5)
@@ -247,6 +249,13 @@ def main():
         torch.cuda.empty_cache()
         return dt, mom
 
+    if args.only == "learned":
+        net, _ = train_network(torch, lb, train=not args.untrained)
+        dt, _ = run("f32s", "caosoa", args.steps, args.warmup, net=net)
+        print(json.dumps({"only": args.only, "mlups": nsites * args.steps / dt / 1e6,
+                          "ms_per_step": dt / args.steps * 1e3, "fallback_fraction": counts.get("fallback_fraction")}))
+        net.close()
+        return
     if args.only:
         parts = args.only.split(":")
         dt, _ = run(parts[0], parts[1], args.steps, args.warmup, split=len(parts) > 2)
@@ -260,7 +269,7 @@ def main():
     t_launch = dt / args.steps
     alg_bytes = bytes_per_site("f64", fused=True) * nsites
     achieved = alg_bytes / t_launch / 1e9
-    traffic = traffic_entry("k_step_f64_caosoa", nsites)
+    traffic = traffic_entry("k_step_f64_caosoa_2048x2048", nsites)
 
     out = {
         "metric": METRIC, "value": mlups, "unit": "MLUPS", "n_gpus": 1, "steps": args.steps,

@@ -26,11 +26,18 @@ import statistics
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 
-def source_digest() -> str:
+CSRC = os.path.join(ROOT, "paper_1804_01918_amd", "csrc")
+# Sources of the plain lattice kernels and of the learned ones.
+PLAIN_SOURCES = ("lb_model.hpp", "lb_layout.hpp", "lb_collide.hpp", "lb_kernels.hpp", "lb_lattice.hip")
+LEARNED_SOURCES = PLAIN_SOURCES + ("lb_learned.hpp", "mlp_common.hpp", "mlp_infer.hpp", "lb_mlp_state.hpp")
+
+
+def source_digest(files=PLAIN_SOURCES) -> str:
+    """Digest of the named files under csrc/ (the sources a kernel is built from)."""
     h = hashlib.sha256()
-    for path in sorted(glob.glob(os.path.join(ROOT, "paper_1804_01918_amd", "csrc", "*"))):
-        with open(path, "rb") as fh:
-            h.update(os.path.basename(path).encode())
+    for name in sorted(files):
+        with open(os.path.join(CSRC, name), "rb") as fh:
+            h.update(name.encode())
             h.update(fh.read())
     return h.hexdigest()[:16]
 
@@ -85,7 +92,12 @@ def main():
     ap.add_argument("--cmd", required=True, help="the commands that produced the inputs")
     ap.add_argument("--md", required=True)
     ap.add_argument("--json", required=True)
+    ap.add_argument("--sources", choices=("plain", "learned"), default="plain",
+                    help="which kernel sources the digest of the entry covers")
+    ap.add_argument("--alg-flops", type=float, default=0.0, help="algorithmic matrix-core flops per launch")
     a = ap.parse_args()
+    files = PLAIN_SOURCES if a.sources == "plain" else LEARNED_SOURCES
+    digest = source_digest(files)
 
     durs = kernel_durations(a.trace)
     kname, kd = _pick(durs, a.match)
@@ -97,9 +109,12 @@ def main():
         lines.append(f"| `{name[:110]}` | {len(v)} | {statistics.fmean(v):.2f} | {min(v):.2f} | {max(v):.2f} |")
     lines += ["", f"Dominant kernel `{kname}`: average {avg_us:.2f} us per launch; "
               f"algorithmic bytes per launch {a.alg_bytes} -> {a.alg_bytes / (avg_us * 1e-6) / 1e9:.0f} GB/s.", ""]
+    if a.alg_flops:
+        lines += [f"Algorithmic matrix-core flops per launch {a.alg_flops:.4g} -> "
+                  f"{a.alg_flops / (avg_us * 1e-6) / 1e12:.1f} TFLOP/s.", ""]
 
     entry = {"kernel": kname, "sites": a.sites, "avg_launch_us": avg_us,
-             "algorithmic_bytes_per_launch": a.alg_bytes}
+             "algorithmic_bytes_per_launch": a.alg_bytes, "source_files": list(files), "source_digest": digest}
     if a.fetch and a.write and a.copy_fetch and a.copy_write and a.copy_bytes:
         _, fk = _pick(counter_per_dispatch(a.fetch, "FETCH_SIZE"), a.match)
         _, wk = _pick(counter_per_dispatch(a.write, "WRITE_SIZE"), a.match)
@@ -122,16 +137,16 @@ def main():
                   f"| HBM read per launch (scaled) | {read_b:.4g} B |",
                   f"| HBM write per launch (scaled) | {write_b:.4g} B |",
                   f"| HBM total / algorithmic | {(read_b + write_b) / a.alg_bytes:.4f} |", ""]
-    lines += [f"Kernel sources digest: `{source_digest()}`", ""]
+    lines += [f"Kernel sources ({', '.join(files)}) digest: `{digest}`", ""]
     with open(a.md, "w") as fh:
         fh.write("\n".join(lines))
 
-    rec = {"source_digest": source_digest(), "kernels": {}}
+    rec = {"kernels": {}}
     if os.path.exists(a.json):
         with open(a.json) as fh:
-            old = json.load(fh)
-        if old.get("source_digest") == rec["source_digest"]:
-            rec = old
+            rec = json.load(fh)
+        rec.pop("source_digest", None)
+        rec.setdefault("kernels", {})
     rec["kernels"][a.name] = entry
     with open(a.json, "w") as fh:
         json.dump(rec, fh, indent=1, sort_keys=True)
