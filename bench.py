@@ -201,6 +201,8 @@ def main():
     ap.add_argument("--no-variants", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-learned", action="store_true")
+    ap.add_argument("--threshold", type=float, default=None,
+                    help="with --only learned: fallback threshold (default: the benchmark's)")
     ap.add_argument("--untrained", action="store_true",
                     help="with --only learned: skip the training (counter runs; HBM bytes do not depend on it)")
     ap.add_argument("--no-scale", action="store_true")
@@ -251,7 +253,8 @@ def main():
 
     if args.only == "learned":
         net, _ = train_network(torch, lb, train=not args.untrained)
-        dt, _ = run("f32s", "caosoa", args.steps, args.warmup, net=net)
+        dt, _ = run("f32s", "caosoa", args.steps, args.warmup, net=net,
+                    threshold=THRESHOLD if args.threshold is None else args.threshold)
         print(json.dumps({"only": args.only, "mlups": nsites * args.steps / dt / 1e6,
                           "ms_per_step": dt / args.steps * 1e3, "fallback_fraction": counts.get("fallback_fraction")}))
         net.close()

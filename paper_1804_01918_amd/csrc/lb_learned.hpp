@@ -95,17 +95,20 @@ __global__ __launch_bounds__(LBLOCK) __attribute__((amdgpu_waves_per_eu(2, 2))) 
         Stencil<L, float, VL> st;
         if (active) st.setup(xrow, r, g);
         // first gather: standardised network inputs (loads that keep the lines cached)
+        {
+            float in[Q];
 #pragma unroll
-        for (int p = 0; p < Q; ++p)
-            mlp::stage_input(X, net, p, active ? P::template load<false>(st.src(src, p, g), p) : 0.0f);
-        mlp::stage_padding(X);
+            for (int p = 0; p < Q; ++p) in[p] = active ? P::template load<false>(st.src(src, p, g), p) : 0.0f;
+            mlp::stage_inputs(X, net, in);
+        }
         mlp::network_outputs(net, X);
         // second gather: the populations for projection and relaxation
         float v[Q];
 #pragma unroll
         for (int p = 0; p < Q; ++p) v[p] = active ? P::template load<L::stream_loads>(st.src(src, p, g), p) : 0.0f;
-        const mlp::Learned lr = mlp::learned_equilibrium(v, net, X, threshold);
-        const bool fb = active && lr.verdict.fallback;
+        float gh[Q];
+        const mlp::Verdict vd = mlp::learned_equilibrium(v, net, X, threshold, gh);
+        const bool fb = active && vd.fallback;
         if (active) {
             double d[Q];
             auto store = [&](int p, float res) {
@@ -116,7 +119,7 @@ __global__ __launch_bounds__(LBLOCK) __attribute__((amdgpu_waves_per_eu(2, 2))) 
                 collide_site<P, COMP>(v, om, store);
             } else {
 #pragma unroll
-                for (int p = 0; p < Q; ++p) store(p, __builtin_fmaf(om, mlp::learned_value(lr, net, p) - v[p], v[p]));
+                for (int p = 0; p < Q; ++p) store(p, __builtin_fmaf(om, gh[p] - v[p], v[p]));
             }
             if constexpr (AUDIT) audit_site(d, acc);
         }
@@ -149,23 +152,26 @@ __global__ __launch_bounds__(LBLOCK) __attribute__((amdgpu_waves_per_eu(2, 2))) 
         const bool active = r < g.ly;
         Stencil<L, float, VL> st;
         if (active) st.setup(xrow, r, g);
+        {
+            float in[Q];
 #pragma unroll
-        for (int p = 0; p < Q; ++p)
-            mlp::stage_input(X, net, p, active ? P::template load<false>(st.own(buf, p, g), p) : 0.0f);
-        mlp::stage_padding(X);
+            for (int p = 0; p < Q; ++p) in[p] = active ? P::template load<false>(st.own(buf, p, g), p) : 0.0f;
+            mlp::stage_inputs(X, net, in);
+        }
         mlp::network_outputs(net, X);
         float v[Q];
 #pragma unroll
         for (int p = 0; p < Q; ++p) v[p] = active ? P::template load<L::stream_loads>(st.own(buf, p, g), p) : 0.0f;
-        const mlp::Learned lr = mlp::learned_equilibrium(v, net, X, threshold);
-        const bool fb = active && lr.verdict.fallback;
+        float gh[Q];
+        const mlp::Verdict vd = mlp::learned_equilibrium(v, net, X, threshold, gh);
+        const bool fb = active && vd.fallback;
         if (active) {
             auto store = [&](int p, float res) { P::template store<L::stream_stores>(st.own(buf, p, g), p, res); };
             if (fb) {
                 collide_site<P, COMP>(v, om, store);
             } else {
 #pragma unroll
-                for (int p = 0; p < Q; ++p) store(p, __builtin_fmaf(om, mlp::learned_value(lr, net, p) - v[p], v[p]));
+                for (int p = 0; p < Q; ++p) store(p, __builtin_fmaf(om, gh[p] - v[p], v[p]));
             }
         }
         nfb += __popcll(__ballot(fb));

@@ -200,6 +200,24 @@ __global__ void k_mlp_stats_final(const double* __restrict__ partials, int nbloc
     }
 }
 
+// Folded standardisation for inference (Net::fnorm), rounded once from FP64:
+// z_std = g a + b with a = 1/(sd_z w), b = -mean_z/sd_z; d = o A + B with
+// A = w sd_y, B = w mean_y.
+__global__ void k_mlp_fold_norm(const float* __restrict__ norm, float* __restrict__ fnorm)
+{
+    const int p = threadIdx.x;
+    if (p >= 64) return;
+    if (p >= Q) {
+        fnorm[p] = fnorm[64 + p] = fnorm[128 + p] = fnorm[192 + p] = 0.0f;
+        return;
+    }
+    const double w = weight(p);
+    fnorm[p] = (float)((double)norm[64 + p] / w);
+    fnorm[64 + p] = (float)(-(double)norm[p] * (double)norm[64 + p]);
+    fnorm[128 + p] = (float)(w * (double)norm[192 + p]);
+    fnorm[192 + p] = (float)(w * (double)norm[128 + p]);
+}
+
 // ---- forward and backward of one training workgroup -------------------------------
 // 32 samples, 4 wavefronts. Sample s of step-batch position b is pair
 // (a (start + b) + c) mod n. Writes the workgroup's gradient (all NPARAM
@@ -465,24 +483,28 @@ __global__ __launch_bounds__(TB) __attribute__((amdgpu_waves_per_eu(2, 2))) void
     uint16_t* X = lds[threadIdx.x >> 6];
     const int64_t s = (int64_t)blockIdx.x * TB + threadIdx.x;
     const bool active = s < n;
+    {
+        float in[Q];
 #pragma unroll
-    for (int p = 0; p < Q; ++p) stage_input(X, net, p, active ? pre[s * Q + p] : 0.0f);
-    stage_padding(X);
+        for (int p = 0; p < Q; ++p) in[p] = active ? pre[s * Q + p] : 0.0f;
+        stage_inputs(X, net, in);
+    }
     network_outputs(net, X);
     float g[Q];
 #pragma unroll
     for (int p = 0; p < Q; ++p) g[p] = active ? pre[s * Q + p] : 0.0f;
-    const Learned lr = learned_equilibrium(g, net, X, threshold);
+    float gh[Q];
+    const Verdict vd = learned_equilibrium(g, net, X, threshold, gh);
     if (!active) return;
-    if (lr.verdict.fallback) {
+    if (vd.fallback) {
         const Macro<float> m = macro_from_raw<float, true>(raw_moments_compensated(g));
         relax_emit<float, true>(g, m, 1.0f, 0.0f, [&](int p, float v) { geq[s * Q + p] = v; });
     } else {
 #pragma unroll
-        for (int p = 0; p < Q; ++p) geq[s * Q + p] = learned_value(lr, net, p);
+        for (int p = 0; p < Q; ++p) geq[s * Q + p] = gh[p];
     }
-    if (res) res[s] = lr.verdict.residual;
-    if (fb) fb[s] = lr.verdict.fallback ? 1 : 0;
+    if (res) res[s] = vd.residual;
+    if (fb) fb[s] = vd.fallback ? 1 : 0;
 }
 
 // ---- host side ----------------------------------------------------------------------
@@ -508,8 +530,14 @@ int mcheck(lb_mlp* m, const char* what)
 
 size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
 
+int fold_norm(lb_mlp* m)
+{
+    hipLaunchKernelGGL(k_mlp_fold_norm, dim3(1), dim3(64), 0, m->stream, (const float*)m->norm, m->fnorm);
+    return mcheck(m, "folding the standardisation");
+}
+
 struct WsLayout {
-    size_t params, m, v, W1b, W2b, W3b, W2t, W3t, W2p, W3p, norm, partials, lossp, loss_epoch, stats, grad, total;
+    size_t params, m, v, W1b, W2b, W3b, W2t, W3t, W2p, W3p, norm, fnorm, partials, lossp, loss_epoch, stats, grad, total;
 };
 
 WsLayout workspace_layout(int max_batch)
@@ -533,6 +561,7 @@ WsLayout workspace_layout(int max_batch)
     l.W2p = take(HID * HID * 2);
     l.W3p = take(NOUT * HID * 2);
     l.norm = take(4 * 64 * 4);
+    l.fnorm = take(4 * 64 * 4);
     l.partials = take((size_t)max_wg * NPARAM_PAD * 4);
     l.lossp = take((size_t)max_wg * 8);
     l.loss_epoch = take((size_t)MAX_EPOCHS * 2 * 8);
@@ -647,6 +676,7 @@ int lb_mlp_create(lb_mlp** out, void* workspace, size_t bytes, int32_t max_batch
     m->W2p = (uint16_t*)(ws + l.W2p);
     m->W3p = (uint16_t*)(ws + l.W3p);
     m->norm = (float*)(ws + l.norm);
+    m->fnorm = (float*)(ws + l.fnorm);
     m->partials = (float*)(ws + l.partials);
     m->lossp = (double*)(ws + l.lossp);
     m->loss_epoch = (double*)(ws + l.loss_epoch);
@@ -671,6 +701,7 @@ int lb_mlp_create(lb_mlp** out, void* workspace, size_t bytes, int32_t max_batch
     }
     int rc = reset_adam(m);
     if (rc == LB_OK) rc = launch_pack(m);
+    if (rc == LB_OK) rc = fold_norm(m);
     if (rc != LB_OK) {
         snprintf(g_mlp_err, sizeof g_mlp_err, "%s", m->err);
         delete m;
@@ -732,7 +763,7 @@ int lb_mlp_set_normalization(lb_mlp* m, const float* host_norm)
     if (hipMemcpyAsync(m->norm, norm, sizeof norm, hipMemcpyHostToDevice, m->stream) != hipSuccess ||
         hipStreamSynchronize(m->stream) != hipSuccess)
         return mfail(m, LB_EDEVICE, "lb_mlp_set_normalization: copy failed");
-    return LB_OK;
+    return fold_norm(m);
 }
 
 int lb_mlp_get_normalization(lb_mlp* m, float* host_norm)
@@ -763,7 +794,8 @@ int lb_mlp_fit_normalization(lb_mlp* m, const float* pre, const float* post, int
         hipLaunchKernelGGL(k_mlp_stats_final, dim3(1), dim3(128), 0, m->stream, (const double*)partials, nb, n, pass,
                            mean, m->norm);
     }
-    return mcheck(m, "lb_mlp_fit_normalization");
+    const int rc = mcheck(m, "lb_mlp_fit_normalization");
+    return rc == LB_OK ? fold_norm(m) : rc;
 }
 
 int lb_mlp_gradient(lb_mlp* m, const float* pre, const float* post, int32_t n, double tau, float* host_grad,

@@ -26,6 +26,7 @@ struct lb_mlp {
     uint16_t* W2p;
     uint16_t* W3p;
     float* norm;          // [4][64]
+    float* fnorm;         // [4][64], folded from norm for inference (Net::fnorm)
     float* partials;      // [max_wg][NPARAM_PAD]
     double* lossp;        // [max_wg]
     double* loss_epoch;   // [MAX_EPOCHS][2]: sum, count
@@ -46,6 +47,7 @@ struct lb_mlp {
         n.W3p = W3p;
         n.params = params;
         n.norm = norm;
+        n.fnorm = fnorm;
         return n;
     }
 };

@@ -39,13 +39,10 @@ constexpr float GELU_A = 0.044715f;
 typedef __attribute__((__vector_size__(8 * sizeof(__bf16)))) __bf16 bf16x8;
 typedef __attribute__((__vector_size__(4 * sizeof(float)))) float f32x4;
 
-// FP32 -> BF16 bits, round to nearest even (inputs here are finite).
-__device__ inline uint16_t bf16_bits(float f)
-{
-    uint32_t u = __float_as_uint(f);
-    u += 0x7FFFu + ((u >> 16) & 1u);
-    return (uint16_t)(u >> 16);
-}
+// FP32 -> BF16, round to nearest even (gfx950 converts in hardware,
+// v_cvt_pk_bf16_f32, two values per instruction).
+__device__ inline __bf16 to_bf16(float f) { return (__bf16)f; }
+__device__ inline uint16_t bf16_bits(float f) { return __builtin_bit_cast(uint16_t, to_bf16(f)); }
 __device__ inline float bf16_value(uint16_t b) { return __uint_as_float((uint32_t)b << 16); }
 
 // gelu(a) = 0.5 a (1 + tanh(c (a + A a^3))) written as a / (1 + exp(-2 c (a + A a^3))).
@@ -54,12 +51,15 @@ __device__ inline float gelu(float a)
     const float y = a * __builtin_fmaf(2.0f * GELU_C * GELU_A, a * a, 2.0f * GELU_C);
     return a / (1.0f + __expf(-y));
 }
-// The same with the hardware exponential and reciprocal (about 1 ulp each),
-// for activations that are rounded to BF16 right after.
+// The same with the hardware base-2 exponential and reciprocal (about 1 ulp
+// each) and log2(e) folded into the constants, for activations that are
+// rounded to BF16 right after.
+constexpr float GELU_K1 = -2.0f * 1.44269504088896340736f * GELU_C * GELU_A;
+constexpr float GELU_K2 = -2.0f * 1.44269504088896340736f * GELU_C;
 __device__ inline float gelu_fast(float a)
 {
-    const float y = a * __builtin_fmaf(2.0f * GELU_C * GELU_A, a * a, 2.0f * GELU_C);
-    return a * __builtin_amdgcn_rcpf(1.0f + __builtin_amdgcn_exp2f(-1.44269504088896340736f * y));
+    const float y2 = a * __builtin_fmaf(GELU_K1, a * a, GELU_K2);
+    return a * __builtin_amdgcn_rcpf(1.0f + __builtin_amdgcn_exp2f(y2));
 }
 __device__ inline float gelu_grad(float a)
 {
@@ -123,6 +123,7 @@ struct Net {
     const uint16_t* W3p;  // [48][128]  W3[o][chain_hidden(slot)] at [o][slot], o padded
     const float* params;  // packed FP32 parameters (biases read from here)
     const float* norm;    // [4][64]: mean z, 1/sd z, mean y, sd y
+    const float* fnorm;   // [4][64] folded for inference: 1/(sd_z w), -mean_z/sd_z, w sd_y, w mean_y
     int ld1 = KIN;        // row strides of W1b and of W2p / W3p (the LDS copies are padded)
     int ld23 = HID;
 };

@@ -22,10 +22,15 @@
 namespace d2q37 {
 namespace mlp {
 
-constexpr int LDX = 80;    // row stride (bf16) of the staged inputs of a wavefront's 64 sites
+// Per-wavefront LDS area: the 64 sites' BF16 inputs in rows of LDX values
+// (144 bytes: 16-byte aligned for the fragment loads, and 36 dwords apart so
+// that a quarter-wavefront's 16-byte accesses fall on distinct banks); the
+// FP32 outputs then overwrite it in rows of LDO floats (176 bytes, same
+// property).
+constexpr int LDX = 72;
 constexpr int LDH = 136;   // row stride of staged hidden activations (training)
-constexpr int LDO = 40;    // row stride (floats) of the staged outputs: same bytes as an input row
-constexpr int WAVE_LDS_BYTES = 64 * LDX * 2;  // 10240
+constexpr int LDO = 44;
+constexpr int WAVE_LDS_BYTES = 64 * LDO * 4;  // 11264 >= 64 * LDX * 2
 
 // Orders LDS traffic between the lanes of one wavefront.
 __device__ inline void wave_sync()
@@ -35,23 +40,55 @@ __device__ inline void wave_sync()
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-__device__ inline float4 load4(const float* p) { return *(const float4*)p; }
-
-// Standardised BF16 input of population p (value g) into the lane's row.
-__device__ inline void stage_input(uint16_t* X, const Net& net, int p, float g)
+__device__ inline f32x4 bias4(const float* p)
 {
-    const float z = g * (float)(1.0 / weight(p));
-    X[lane_id() * LDX + p] = bf16_bits((z - net.norm[p]) * net.norm[64 + p]);
+    const float4 v = *(const float4*)p;
+    return f32x4{v.x, v.y, v.z, v.w};
 }
-__device__ inline void stage_padding(uint16_t* X)
+
+// The folded standardisation (Net::fnorm) is constant during a kernel and
+// read at uniform addresses: through the constant address space it comes in
+// by scalar loads into SGPRs. The empty asm gives each use a fresh pointer,
+// so the loads stay next to their use instead of being hoisted out of the
+// tile loop (148 values held across the loop would spill).
+typedef const float __attribute__((address_space(4))) cfloat;
+__device__ inline cfloat* folded(const Net& net)
 {
+    uint64_t a = (uint64_t)net.fnorm;
+    asm volatile("" : "+s"(a));
+    return (cfloat*)a;
+}
+
+typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+__device__ inline uint32_t pack_bf16(float a, float b)
+{
+    const bf16x2 v = {to_bf16(a), to_bf16(b)};
+    return __builtin_bit_cast(uint32_t, v);
+}
+
+// Standardised BF16 inputs of the lane's site (shifted populations g) into
+// its row of X, features 37..63 zero: eight 16-byte stores.
+__device__ inline void stage_inputs(uint16_t* X, const Net& net, const float (&g)[Q])
+{
+    cfloat* fz = folded(net);
+    uint32_t w[KIN / 2];
 #pragma unroll
-    for (int f = Q; f < LDX; ++f) X[lane_id() * LDX + f] = 0;
+    for (int j = 0; j < KIN / 2; ++j) {
+        const int p0 = 2 * j, p1 = 2 * j + 1;
+        const float a = p0 < Q ? __builtin_fmaf(g[p0 < Q ? p0 : 0], fz[p0], fz[64 + p0]) : 0.0f;
+        const float b = p1 < Q ? __builtin_fmaf(g[p1 < Q ? p1 : 0], fz[p1], fz[64 + p1]) : 0.0f;
+        w[j] = (p0 < Q) ? pack_bf16(a, b) : 0u;
+    }
+    uint4* row = (uint4*)(X + lane_id() * LDX);
+#pragma unroll
+    for (int q = 0; q < KIN / 8; ++q) row[q] = uint4{w[4 * q], w[4 * q + 1], w[4 * q + 2], w[4 * q + 3]};
 }
 
 // Network outputs of the wavefront's 64 sites. X holds the staged inputs
-// (row per site); on return the same rows hold the standardised outputs as
-// FP32, out[site * LDO + o] for o < 37. Every lane must call it.
+// (row per site); on return the area holds the standardised outputs as
+// FP32, out[site * LDO + o] for o < 37. Every lane must call it. The output
+// rows are longer than the input rows, so the upper half of the sites goes
+// first: its outputs then cover only its own, consumed, inputs.
 __device__ inline void network_outputs(const Net& net, uint16_t* X)
 {
     const int lane = lane_id(), col = lane & 15, quad = lane >> 4;
@@ -61,95 +98,103 @@ __device__ inline void network_outputs(const Net& net, uint16_t* X)
     wave_sync();
 
 #pragma unroll 1
-    for (int half = 0; half < 2; ++half) {
-        uint16_t* Xh = X + half * 32 * LDX;
+    for (int pass = 0; pass < 2; ++pass) {
+        const int half = 1 - pass;
+        const uint16_t* Xh = X + half * 32 * LDX;
 
-        // layer 1: H1^T (128 x 32) = W1 (128 x 64) X^T (64 x 32)
+        // Biases enter as the accumulator of each chain's first product: row
+        // 4 quad + j of tile mt is unit 16 mt + 4 quad + j.
+        // layer 1: H1^T (128 x 32) = W1 (128 x 64) X^T (64 x 32) + b1
         f32x4 acc[8][2];
+        {
+            f32x4 bias[8];
 #pragma unroll
-        for (int mt = 0; mt < 8; ++mt) acc[mt][0] = acc[mt][1] = f32x4{0.f, 0.f, 0.f, 0.f};
+            for (int mt = 0; mt < 8; ++mt) bias[mt] = bias4(b1 + 16 * mt + 4 * quad);
 #pragma unroll
-        for (int ks = 0; ks < 2; ++ks) {
-            __builtin_amdgcn_sched_barrier(0);  // one k block of weight fragments in flight
-            const bf16x8 x0 = frag_im(Xh, LDX, 0, ks * 32), x1 = frag_im(Xh, LDX, 16, ks * 32);
+            for (int ks = 0; ks < 2; ++ks) {
+                __builtin_amdgcn_sched_barrier(0);  // one k block of weight fragments in flight
+                const bf16x8 x0 = frag_im(Xh, LDX, 0, ks * 32), x1 = frag_im(Xh, LDX, 16, ks * 32);
 #pragma unroll
-            for (int mt = 0; mt < 8; ++mt) {
-                const bf16x8 a = frag_im(net.W1b, net.ld1, mt * 16, ks * 32);
-                acc[mt][0] = mfma(a, x0, acc[mt][0]);
-                acc[mt][1] = mfma(a, x1, acc[mt][1]);
+                for (int mt = 0; mt < 8; ++mt) {
+                    const bf16x8 a = frag_im(net.W1b, net.ld1, mt * 16, ks * 32);
+                    acc[mt][0] = mfma(a, x0, ks == 0 ? bias[mt] : acc[mt][0]);
+                    acc[mt][1] = mfma(a, x1, ks == 0 ? bias[mt] : acc[mt][1]);
+                }
             }
         }
         __builtin_amdgcn_sched_barrier(0);
-        // bias, GELU, BF16 into the B fragments of the next layer
+        // GELU, BF16 into the B fragments of the next layer
         bf16x8 hb[4][2];
 #pragma unroll
-        for (int kb = 0; kb < 4; ++kb) {
-            const float4 lo = load4(b1 + 32 * kb + 4 * quad), hi = load4(b1 + 32 * kb + 16 + 4 * quad);
-            const float bl[4] = {lo.x, lo.y, lo.z, lo.w}, bh[4] = {hi.x, hi.y, hi.z, hi.w};
+        for (int kb = 0; kb < 4; ++kb)
 #pragma unroll
             for (int nt = 0; nt < 2; ++nt)
 #pragma unroll
                 for (int j = 0; j < 4; ++j) {
-                    hb[kb][nt][j] = __builtin_bit_cast(__bf16, bf16_bits(gelu_fast(acc[2 * kb][nt][j] + bl[j])));
-                    hb[kb][nt][4 + j] = __builtin_bit_cast(__bf16, bf16_bits(gelu_fast(acc[2 * kb + 1][nt][j] + bh[j])));
+                    hb[kb][nt][j] = to_bf16(gelu_fast(acc[2 * kb][nt][j]));
+                    hb[kb][nt][4 + j] = to_bf16(gelu_fast(acc[2 * kb + 1][nt][j]));
                 }
-        }
 
-        // layer 2: H2^T = W2 H1^T (weight columns in chained order)
+        // layer 2: H2^T = W2 H1^T + b2 (weight columns in chained order)
+        {
+            f32x4 bias[8];
 #pragma unroll
-        for (int mt = 0; mt < 8; ++mt) acc[mt][0] = acc[mt][1] = f32x4{0.f, 0.f, 0.f, 0.f};
+            for (int mt = 0; mt < 8; ++mt) bias[mt] = bias4(b2 + 16 * mt + 4 * quad);
 #pragma unroll
-        for (int kb = 0; kb < 4; ++kb) {
-            __builtin_amdgcn_sched_barrier(0);
+            for (int kb = 0; kb < 4; ++kb) {
+                __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
-            for (int mt = 0; mt < 8; ++mt) {
-                const bf16x8 a = frag_im(net.W2p, net.ld23, mt * 16, kb * 32);
-                acc[mt][0] = mfma(a, hb[kb][0], acc[mt][0]);
-                acc[mt][1] = mfma(a, hb[kb][1], acc[mt][1]);
+                for (int mt = 0; mt < 8; ++mt) {
+                    const bf16x8 a = frag_im(net.W2p, net.ld23, mt * 16, kb * 32);
+                    acc[mt][0] = mfma(a, hb[kb][0], kb == 0 ? bias[mt] : acc[mt][0]);
+                    acc[mt][1] = mfma(a, hb[kb][1], kb == 0 ? bias[mt] : acc[mt][1]);
+                }
             }
         }
         __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
-        for (int kb = 0; kb < 4; ++kb) {
-            const float4 lo = load4(b2 + 32 * kb + 4 * quad), hi = load4(b2 + 32 * kb + 16 + 4 * quad);
-            const float bl[4] = {lo.x, lo.y, lo.z, lo.w}, bh[4] = {hi.x, hi.y, hi.z, hi.w};
+        for (int kb = 0; kb < 4; ++kb)
 #pragma unroll
             for (int nt = 0; nt < 2; ++nt)
 #pragma unroll
                 for (int j = 0; j < 4; ++j) {
-                    hb[kb][nt][j] = __builtin_bit_cast(__bf16, bf16_bits(gelu_fast(acc[2 * kb][nt][j] + bl[j])));
-                    hb[kb][nt][4 + j] = __builtin_bit_cast(__bf16, bf16_bits(gelu_fast(acc[2 * kb + 1][nt][j] + bh[j])));
+                    hb[kb][nt][j] = to_bf16(gelu_fast(acc[2 * kb][nt][j]));
+                    hb[kb][nt][4 + j] = to_bf16(gelu_fast(acc[2 * kb + 1][nt][j]));
                 }
-        }
 
-        // layer 3: O^T (48 x 32) = W3 H2^T
+        // layer 3: O^T (48 x 32) = W3 H2^T + b3 (outputs 37..47 zero)
         f32x4 acc3[3][2];
+        {
+            f32x4 bias[3];
 #pragma unroll
-        for (int mt = 0; mt < 3; ++mt) acc3[mt][0] = acc3[mt][1] = f32x4{0.f, 0.f, 0.f, 0.f};
+            for (int mt = 0; mt < 3; ++mt)
 #pragma unroll
-        for (int kb = 0; kb < 4; ++kb) {
-            __builtin_amdgcn_sched_barrier(0);
+                for (int i = 0; i < 4; ++i) {
+                    const int o = 16 * mt + 4 * quad + i;
+                    bias[mt][i] = o < Q ? b3[o < Q ? o : 0] : 0.0f;
+                }
 #pragma unroll
-            for (int mt = 0; mt < 3; ++mt) {
-                const bf16x8 a = frag_im(net.W3p, net.ld23, mt * 16, kb * 32);
-                acc3[mt][0] = mfma(a, hb[kb][0], acc3[mt][0]);
-                acc3[mt][1] = mfma(a, hb[kb][1], acc3[mt][1]);
+            for (int kb = 0; kb < 4; ++kb) {
+                __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+                for (int mt = 0; mt < 3; ++mt) {
+                    const bf16x8 a = frag_im(net.W3p, net.ld23, mt * 16, kb * 32);
+                    acc3[mt][0] = mfma(a, hb[kb][0], kb == 0 ? bias[mt] : acc3[mt][0]);
+                    acc3[mt][1] = mfma(a, hb[kb][1], kb == 0 ? bias[mt] : acc3[mt][1]);
+                }
             }
         }
         wave_sync();  // the half's input rows are dead before its outputs overwrite them
-        float* O = (float*)Xh;
+        float* O = (float*)X + half * 32 * LDO;
 #pragma unroll
         for (int mt = 0; mt < 3; ++mt) {
             const int o = mt * 16 + 4 * quad;
             if (o < LDO) {
-                float bb[4];
-#pragma unroll
-                for (int i = 0; i < 4; ++i) bb[i] = (o + i) < Q ? b3[o + i] : 0.f;
 #pragma unroll
                 for (int nt = 0; nt < 2; ++nt) {
                     const int site = 16 * nt + col;
-                    *(float4*)(O + site * LDO + o) = float4{acc3[mt][nt][0] + bb[0], acc3[mt][nt][1] + bb[1],
-                                                           acc3[mt][nt][2] + bb[2], acc3[mt][nt][3] + bb[3]};
+                    *(float4*)(O + site * LDO + o) = float4{acc3[mt][nt][0], acc3[mt][nt][1], acc3[mt][nt][2],
+                                                           acc3[mt][nt][3]};
                 }
             }
         }
@@ -199,36 +244,28 @@ struct Verdict {
     float residual;
 };
 
-// The learned equilibrium of a lane's site, evaluated on demand from the
-// staged network outputs: g_hat_p = d_p + P(g - d)_p, d_p = w_p (mean_y +
-// sd_y o_p).
-struct Learned {
-    const float* row;
-    ConservedCoef k;
-    Verdict verdict;
-};
 
-__device__ inline float learned_d(const Net& net, const float* row, int p)
+// Learned equilibrium gh of each lane's site from its populations g and the
+// network outputs staged by network_outputs: gh_p = d_p + P(g - d)_p with
+// d_p = w_p (mean_y + sd_y o_p) (folded: o_p w_p sd_y + w_p mean_y), so gh
+// has the mass, momentum and energy of g. Returns the fallback verdict: residual against the equilibrium stress
+// and heat flux of (rho, u, T), training box on rho, |u|, T.
+__device__ inline Verdict learned_equilibrium(const float (&g)[Q], const Net& net, const uint16_t* X, float threshold,
+                                              float (&gh)[Q])
 {
-    return mulk(__builtin_fmaf(net.norm[192 + p], row[p], net.norm[128 + p]), weight(p));
-}
-__device__ inline float learned_value(const Learned& L, const Net& net, int p)
-{
-    return learned_d(net, L.row, p) + conserved_value(p, L.k);
-}
-
-// Projection coefficients and fallback verdict of each lane's site from its
-// populations g and the network outputs staged by network_outputs (residual
-// against the equilibrium stress and heat flux of (rho, u, T); training box
-// on rho, |u|, T).
-__device__ inline Learned learned_equilibrium(const float (&g)[Q], const Net& net, const uint16_t* X, float threshold)
-{
-    Learned L;
-    L.row = (const float*)X + lane_id() * LDO;
+    const float4* row = (const float4*)X + lane_id() * (LDO / 4);
+    cfloat* fy = folded(net);
+    float o[4 * ((Q + 3) / 4)];
+#pragma unroll
+    for (int q = 0; q < (Q + 3) / 4; ++q) {
+        const float4 r = row[q];
+        o[4 * q] = r.x, o[4 * q + 1] = r.y, o[4 * q + 2] = r.z, o[4 * q + 3] = r.w;
+    }
     float d0 = 0.f, dx = 0.f, dy = 0.f, de = 0.f;
 #pragma unroll
     for (int p = 0; p < Q; ++p) {
-        const float d = learned_d(net, L.row, p);
+        const float d = __builtin_fmaf(o[p], fy[128 + p], fy[192 + p]);
+        gh[p] = d;
         d0 += d;
         if (CX[p] != 0) dx = __builtin_fmaf((float)CX[p], d, dx);
         if (CY[p] != 0) dy = __builtin_fmaf((float)CY[p], d, dy);
@@ -236,7 +273,7 @@ __device__ inline Learned learned_equilibrium(const float (&g)[Q], const Net& ne
     }
     const Conserved mg = conserved_moments(g);
     const float md0 = d0, mdx = mulk(dx, R), mdy = mulk(dy, R), mdE = mulk(de, R2) - 2.0f * d0;
-    L.k = conserved_coef(mg.m0 - md0, mg.mx - mdx, mg.my - mdy, mg.mE - mdE);
+    const ConservedCoef k = conserved_coef(mg.m0 - md0, mg.mx - mdx, mg.my - mdy, mg.mE - mdE);
 
     const float rho = 1.0f + mg.m0;
     const float ux = mg.mx / rho, uy = mg.my / rho;
@@ -245,22 +282,24 @@ __device__ inline Learned learned_equilibrium(const float (&g)[Q], const Net& ne
     float sxy = 0.f, snn = 0.f, sqx = 0.f, sqy = 0.f;  // lattice units
 #pragma unroll
     for (int p = 0; p < Q; ++p) {
-        const float gh = learned_value(L, net, p);
-        if (CX[p] * CY[p] != 0) sxy = __builtin_fmaf((float)(CX[p] * CY[p]), gh, sxy);
+        const float v = gh[p] + conserved_value(p, k);
+        gh[p] = v;
+        if (CX[p] * CY[p] != 0) sxy = __builtin_fmaf((float)(CX[p] * CY[p]), v, sxy);
         if (CX[p] * CX[p] - CY[p] * CY[p] != 0)
-            snn = __builtin_fmaf((float)(CX[p] * CX[p] - CY[p] * CY[p]), gh, snn);
-        if (CX[p] != 0) sqx = __builtin_fmaf((float)(CX[p] * c2_of(p)), gh, sqx);
-        if (CY[p] != 0) sqy = __builtin_fmaf((float)(CY[p] * c2_of(p)), gh, sqy);
+            snn = __builtin_fmaf((float)(CX[p] * CX[p] - CY[p] * CY[p]), v, snn);
+        if (CX[p] != 0) sqx = __builtin_fmaf((float)(CX[p] * c2_of(p)), v, sqx);
+        if (CY[p] != 0) sqy = __builtin_fmaf((float)(CY[p] * c2_of(p)), v, sqy);
     }
     const float q4 = u2 + 4.0f * T;
     const float r1 = fabsf(mulk(sxy, R2) - rho * ux * uy);
     const float r2 = fabsf(mulk(snn, R2) - rho * (ux * ux - uy * uy));
     const float r3 = fabsf(mulk(sqx, R * R2) - rho * ux * q4);
     const float r4 = fabsf(mulk(sqy, R * R2) - rho * uy * q4);
-    L.verdict.residual = fmaxf(fmaxf(r1, r2), fmaxf(r3, r4));
+    Verdict vd;
+    vd.residual = fmaxf(fmaxf(r1, r2), fmaxf(r3, r4));
     const bool in_box = rho >= 0.9f && rho <= 1.1f && u2 <= 0.01f && T >= 0.9f && T <= 1.1f;
-    L.verdict.fallback = !in_box || !(L.verdict.residual <= threshold);
-    return L;
+    vd.fallback = !in_box || !(vd.residual <= threshold);
+    return vd;
 }
 
 }  // namespace mlp
