@@ -92,20 +92,22 @@ __global__ __launch_bounds__(LBLOCK) __attribute__((amdgpu_waves_per_eu(2, 2))) 
         const int xrow = (int)(tile / g.tpr);
         const int r = (int)(tile - (int64_t)xrow * g.tpr) * LBLOCK + (int)threadIdx.x;
         const bool active = r < g.ly;
+        // lanes past the row end read the row's last site (valid addresses,
+        // no per-load predication) and store nothing
         Stencil<L, float, VL> st;
-        if (active) st.setup(xrow, r, g);
+        st.setup(xrow, active ? r : g.ly - 1, g);
         // first gather: standardised network inputs (loads that keep the lines cached)
         {
             float in[Q];
 #pragma unroll
-            for (int p = 0; p < Q; ++p) in[p] = active ? P::template load<false>(st.src(src, p, g), p) : 0.0f;
+            for (int p = 0; p < Q; ++p) in[p] = P::template load<false>(st.src(src, p, g), p);
             mlp::stage_inputs(X, net, in);
         }
         mlp::network_outputs(net, X);
         // second gather: the populations for projection and relaxation
         float v[Q];
 #pragma unroll
-        for (int p = 0; p < Q; ++p) v[p] = active ? P::template load<L::stream_loads>(st.src(src, p, g), p) : 0.0f;
+        for (int p = 0; p < Q; ++p) v[p] = P::template load<L::stream_loads>(st.src(src, p, g), p);
         float gh[Q];
         const mlp::Verdict vd = mlp::learned_equilibrium(v, net, X, threshold, gh);
         const bool fb = active && vd.fallback;
@@ -150,18 +152,20 @@ __global__ __launch_bounds__(LBLOCK) __attribute__((amdgpu_waves_per_eu(2, 2))) 
         const int xrow = (int)(tile / g.tpr);
         const int r = (int)(tile - (int64_t)xrow * g.tpr) * LBLOCK + (int)threadIdx.x;
         const bool active = r < g.ly;
+        // lanes past the row end read the row's last site (valid addresses,
+        // no per-load predication) and store nothing
         Stencil<L, float, VL> st;
-        if (active) st.setup(xrow, r, g);
+        st.setup(xrow, active ? r : g.ly - 1, g);
         {
             float in[Q];
 #pragma unroll
-            for (int p = 0; p < Q; ++p) in[p] = active ? P::template load<false>(st.own(buf, p, g), p) : 0.0f;
+            for (int p = 0; p < Q; ++p) in[p] = P::template load<false>(st.own(buf, p, g), p);
             mlp::stage_inputs(X, net, in);
         }
         mlp::network_outputs(net, X);
         float v[Q];
 #pragma unroll
-        for (int p = 0; p < Q; ++p) v[p] = active ? P::template load<L::stream_loads>(st.own(buf, p, g), p) : 0.0f;
+        for (int p = 0; p < Q; ++p) v[p] = P::template load<L::stream_loads>(st.own(buf, p, g), p);
         float gh[Q];
         const mlp::Verdict vd = mlp::learned_equilibrium(v, net, X, threshold, gh);
         const bool fb = active && vd.fallback;
