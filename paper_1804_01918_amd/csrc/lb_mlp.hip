@@ -422,9 +422,16 @@ __global__ __launch_bounds__(TB) void k_mlp_fwdbwd(const float* __restrict__ pre
     }
 }
 
-// Sum of the workgroup gradients (fixed order), then either an Adam step
-// (mode 0; parameters and their BF16 copies updated, the step's loss added
-// to loss_epoch[epoch]) or a copy of the gradient to grad (mode 1).
+// Sum of the workgroup gradients, then either an Adam step (mode 0;
+// parameters and their BF16 copies updated, the step's loss added to
+// loss_epoch[epoch]) or a copy of the gradient to grad (mode 1). A workgroup
+// takes UPD_PARAMS parameters; its UPD_SLICES slices of lanes sum the
+// partials w = slice, slice + UPD_SLICES, ... and the slices are then added
+// in slice order (a fixed order: the result is reproducible).
+constexpr int UPD_PARAMS = 32;
+constexpr int UPD_SLICES = TB / UPD_PARAMS;
+constexpr int UPD_GRID = (NPARAM + UPD_PARAMS - 1) / UPD_PARAMS;
+
 __global__ __launch_bounds__(TB) void k_mlp_update(float* __restrict__ params, float* __restrict__ m,
                                                    float* __restrict__ v, const float* __restrict__ partials,
                                                    int nwg, int mode, float lr, float bc1, float bc2,
@@ -435,16 +442,25 @@ __global__ __launch_bounds__(TB) void k_mlp_update(float* __restrict__ params, f
                                                    uint16_t* __restrict__ W3t, uint16_t* __restrict__ W2p,
                                                    uint16_t* __restrict__ W3p)
 {
-    const int i = blockIdx.x * TB + threadIdx.x;
+    __shared__ float part[UPD_SLICES][UPD_PARAMS];
+    const int lp = threadIdx.x % UPD_PARAMS, slice = threadIdx.x / UPD_PARAMS;
+    const int i = blockIdx.x * UPD_PARAMS + lp;
     if (blockIdx.x == 0 && threadIdx.x == 0 && loss_epoch) {
         double s = 0.0;
         for (int w = 0; w < nwg; ++w) s += lossp[w];
         loss_epoch[2 * epoch] += s;
         loss_epoch[2 * epoch + 1] += 1.0;
     }
-    if (i >= NPARAM) return;
     float g = 0.f;
-    for (int w = 0; w < nwg; ++w) g += partials[(int64_t)w * NPARAM_PAD + i];
+    if (i < NPARAM) {
+#pragma unroll 8
+        for (int w = slice; w < nwg; w += UPD_SLICES) g += partials[(int64_t)w * NPARAM_PAD + i];
+    }
+    part[slice][lp] = g;
+    __syncthreads();
+    if (slice != 0 || i >= NPARAM) return;
+#pragma unroll
+    for (int k = 1; k < UPD_SLICES; ++k) g += part[k][lp];
     if (mode == 1) {
         grad[i] = g;
         return;
@@ -806,7 +822,7 @@ int lb_mlp_gradient(lb_mlp* m, const float* pre, const float* post, int32_t n, d
         return mfail(m, LB_EINVAL, "lb_mlp_gradient: n = %d must be a multiple of %d and <= %d", n, TS, m->max_batch);
     int rc = fwdbwd(m, pre, post, n, 1, 0, 0, n, (float)tau);
     if (rc != LB_OK) return rc;
-    hipLaunchKernelGGL(k_mlp_update, dim3((NPARAM + TB - 1) / TB), dim3(TB), 0, m->stream, m->params, m->adam_m,
+    hipLaunchKernelGGL(k_mlp_update, dim3(UPD_GRID), dim3(TB), 0, m->stream, m->params, m->adam_m,
                        m->adam_v, (const float*)m->partials, n / TS, 1, 0.f, 1.f, 1.f, m->grad,
                        (const double*)m->lossp, (double*)nullptr, 0, m->W1b, m->W2b, m->W3b, m->W2t, m->W3t,
                        m->W2p, m->W3p);
@@ -851,7 +867,7 @@ int lb_mlp_train(lb_mlp* m, const float* pre, const float* post, int64_t n, doub
             const double lr_t = (double)lr * 0.5 * (1.0 + cos(M_PI * (double)step / (double)total));
             m->adam_t += 1;
             const double bc1 = 1.0 - pow(0.9, (double)m->adam_t), bc2 = 1.0 - pow(0.999, (double)m->adam_t);
-            hipLaunchKernelGGL(k_mlp_update, dim3((NPARAM + TB - 1) / TB), dim3(TB), 0, m->stream, m->params,
+            hipLaunchKernelGGL(k_mlp_update, dim3(UPD_GRID), dim3(TB), 0, m->stream, m->params,
                                m->adam_m, m->adam_v, (const float*)m->partials, batch / TS, 0, (float)lr_t,
                                (float)bc1, (float)bc2, m->grad, (const double*)m->lossp, m->loss_epoch, e, m->W1b,
                                m->W2b, m->W3b, m->W2t, m->W3t, m->W2p, m->W3p);
