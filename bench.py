@@ -172,6 +172,50 @@ def learned_variant(args, torch, lb, inputs, run, counts, nsites, shear_ref, rt_
     return v, net
 
 
+def time_calls(lat, torch, fn, n: int) -> float:
+    """Seconds for n calls of fn on the lattice's stream (HIP events)."""
+    start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    start.record(lat.stream)
+    for _ in range(n):
+        fn()
+    stop.record(lat.stream)
+    stop.synchronize()
+    return start.elapsed_time(stop) / 1e3
+
+
+# The paper's Table 1 (FP64, separate propagate and collide kernels,
+# 1024 x 8192 lattice): T_prop and T_coll in ms per call.
+TABLE1 = {"KNL 7230 flat/quad": (12.5, 50.3), "KNL 7230 cache/quad": (19.65, 51.42), "P100": (12.5, 24.1),
+          "GK210": (32.3, 71.1), "KNC 7120P": (49.9, 180.9), "E5-2697v4": (98.06, 173.42)}
+
+
+def table1_variant(args, torch, lb, inputs):
+    """The paper's Table 1 workload shape on this GPU: FP64 CAoSoA,
+    1024 x 8192, propagate and collide timed as separate kernels (as the
+    paper does) and fused."""
+    lx, ly = 1024, 8192
+    n = lx * ly
+    fields = [torch.from_numpy(a).cuda() for a in inputs.shear_wave(lx, ly, seed=0)]
+    lat = lb.Lattice(lx, ly, TAU, fields, precision="f64", layout="caosoa")
+    reps = max(10, args.variant_steps)
+    for _ in range(args.warmup):
+        lat.propagate()
+        lat.collide()
+    t_prop = time_calls(lat, torch, lat.propagate, reps) / reps
+    t_coll = time_calls(lat, torch, lat.collide, reps) / reps
+    t_step = time_calls(lat, torch, lambda: lat.step(1), reps) / reps
+    lat.close()
+    del lat, fields
+    torch.cuda.empty_cache()
+    return {"lattice": [lx, ly], "precision": "f64", "layout": "caosoa",
+            "T_prop_ms": t_prop * 1e3, "T_coll_ms": t_coll * 1e3,
+            "propagate_GBs": 2 * 37 * 8 * n / t_prop / 1e9, "collide_mlups": n / t_coll / 1e6,
+            "split_step_mlups": n / (t_prop + t_coll) / 1e6, "fused_step_mlups": n / t_step / 1e6,
+            "paper_table1_ms": {k: {"T_prop": a, "T_coll": b, "global_mlups_from_T": n / ((a + b) * 1e-3) / 1e6}
+                                for k, (a, b) in TABLE1.items()}}
+
+
 def scale_variant(args, torch, inputs, run, counts, net):
     """8192 x 8192 Rayleigh-Taylor-like lattice: FP64, FP32-shifted and the
     learned collide on the same GPU, errors against the FP64 run."""
@@ -311,6 +355,8 @@ def main():
         cb = copy_bandwidth(torch, lb, alg_bytes // 2)
         variants["copy_kernel_gbs"] = cb
         out["roofline"]["frac_of_copy"] = achieved / cb
+
+        variants["table1_1024x8192_f64"] = table1_variant(args, torch, lb, inputs)
 
         # Precision on the thermal Rayleigh-Taylor-like state.
         rt = (LX, LY, [torch.from_numpy(a).cuda() for a in inputs.rayleigh_taylor(LX, LY, seed=0)])

@@ -95,6 +95,9 @@ def main():
     ap.add_argument("--sources", choices=("plain", "learned"), default="plain",
                     help="which kernel sources the digest of the entry covers")
     ap.add_argument("--alg-flops", type=float, default=0.0, help="algorithmic matrix-core flops per launch")
+    ap.add_argument("--valu", default=None,
+                    help="a --pmc run of the SQ_INSTS_VALU_{FMA,MUL,ADD,TRANS}_F64/_F32 counters: vector flops")
+    ap.add_argument("--valu-counters", default="", help="the counter names that run collected (space separated)")
     a = ap.parse_args()
     files = PLAIN_SOURCES if a.sources == "plain" else LEARNED_SOURCES
     digest = source_digest(files)
@@ -112,6 +115,25 @@ def main():
     if a.alg_flops:
         lines += [f"Algorithmic matrix-core flops per launch {a.alg_flops:.4g} -> "
                   f"{a.alg_flops / (avg_us * 1e-6) / 1e12:.1f} TFLOP/s.", ""]
+
+    if a.valu and a.valu_counters:
+        # Each counter counts wavefront instructions; x64 lanes, FMA = 2 flops.
+        vals = {}
+        for cname in a.valu_counters.split():
+            _, cv = _pick(counter_per_dispatch(a.valu, cname), a.match)
+            vals[cname] = statistics.median(cv)
+        flops = 0.0
+        for cname, v in vals.items():
+            if "_FMA_" in cname:
+                flops += 2 * 64 * v
+            elif any(k in cname for k in ("_MUL_", "_ADD_", "_TRANS_")):
+                flops += 64 * v
+        lines += ["## Vector ALU work (--pmc, medians per dispatch)", "", "| counter | per dispatch | per site |",
+                  "|---|---|---|"]
+        for cname, v in vals.items():
+            lines.append(f"| {cname} | {v:.4g} | {64 * v / a.sites:.1f} lane-ops |")
+        lines += ["", f"Counted vector flops (FMA = 2): {flops / a.sites:.0f} per site, "
+                      f"{flops / (avg_us * 1e-6) / 1e12:.2f} TFLOP/s at the traced launch time.", ""]
 
     entry = {"kernel": kname, "sites": a.sites, "avg_launch_us": avg_us,
              "algorithmic_bytes_per_launch": a.alg_bytes, "source_files": list(files), "source_digest": digest}
