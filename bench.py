@@ -216,6 +216,59 @@ def table1_variant(args, torch, lb, inputs):
                                 for k, (a, b) in TABLE1.items()}}
 
 
+def energy_variant(args, torch, lb, fields, net):
+    """Energy on the GPU package's counter around synchronised runs of about
+    2 s each (2048 x 2048 shear wave): per lattice update of the fused step
+    for each form, and, as in the paper's energy figure, per iteration of
+    the separate propagate and collide kernels for each FP64 layout."""
+    from paper_1804_01918_amd.energy import EnergyMeter
+    meter = EnergyMeter(0)
+    out = {"available": meter.available, "reason": meter.reason or None, "fused_step": {},
+           "f64_split_kernels_by_layout": {}}
+    if not meter.available:
+        return out
+
+    def run_for(lat, fn, target_s=2.0):
+        t = time_calls(lat, torch, fn, 20) / 20
+        n = max(50, int(target_s / max(t, 1e-6)))
+
+        def go():
+            for _ in range(n):
+                fn()
+            torch.cuda.synchronize()
+
+        joules, dt = meter.measure(go)
+        return n, joules, dt
+
+    forms = [("f64", None), ("f32s", None), ("f16s", None)] + ([("f32s", net)] if net is not None else [])
+    for prec, nn in forms:
+        lat = lb.Lattice(LX, LY, TAU, fields, precision=prec, layout="caosoa")
+        if nn is not None:
+            lat.set_surrogate(nn, THRESHOLD)
+        lat.step(args.warmup)
+        n, joules, dt = run_for(lat, lambda: lat.step(1))
+        key = ("learned_" if nn is not None else "") + f"{prec}_caosoa"
+        out["fused_step"][key] = {"steps": n, "seconds": dt, "joules": joules, "avg_watts": joules / dt,
+                                  "nJ_per_lattice_update": joules / (LX * LY * n) * 1e9,
+                                  "mlups": LX * LY * n / dt / 1e6}
+        lat.close()
+        del lat
+        torch.cuda.empty_cache()
+    for layout in ("aos", "soa", "csoa", "caosoa"):
+        lat = lb.Lattice(LX, LY, TAU, fields, precision="f64", layout=layout)
+        rec = {}
+        for kname, fn in (("propagate", lat.propagate), ("collide", lat.collide)):
+            n, joules, dt = run_for(lat, fn, 1.0)
+            rec[kname] = {"calls": n, "ms_per_call": dt / n * 1e3, "J_per_iteration": joules / n,
+                          "avg_watts": joules / dt}
+        out["f64_split_kernels_by_layout"][layout] = rec
+        lat.close()
+        del lat
+        torch.cuda.empty_cache()
+    meter.close()
+    return out
+
+
 def scale_variant(args, torch, inputs, run, counts, net):
     """8192 x 8192 Rayleigh-Taylor-like lattice: FP64, FP32-shifted and the
     learned collide on the same GPU, errors against the FP64 run."""
@@ -250,6 +303,7 @@ def main():
     ap.add_argument("--untrained", action="store_true",
                     help="with --only learned: skip the training (counter runs; HBM bytes do not depend on it)")
     ap.add_argument("--no-scale", action="store_true")
+    ap.add_argument("--no-energy", action="store_true")
     ap.add_argument("--scale-steps", type=int, default=500)
     ap.add_argument("--only", default=None, help="precision:layout[:split], or 'learned', to time alone")
     ap.add_argument("--copy-bytes", type=int, default=0,
@@ -376,6 +430,8 @@ def main():
         out["variants"]["learned_f32s_caosoa_fused"] = lv
         if not args.no_scale:
             out["variants"]["scale_8192_rayleigh_taylor"] = scale_variant(args, torch, inputs, run, counts, net)
+        if not args.no_energy:
+            out["variants"]["energy_2048"] = energy_variant(args, torch, lb, fields, net)
         net.close()
 
     if not args.no_cpu:

@@ -208,6 +208,52 @@ def test_learned_step_matches_oracle(consts, oracle_net, kind):
     assert np.max(np.abs(got - ref) / w) <= 2e-3 / TAU
 
 
+def _learned_sampled_parity(consts, oracle_net, lx, ly, layout, kind, sites, seed=2):
+    """One learned step on the GPU (no fallback) against the oracle's learned
+    collide on each sampled site's dependency window."""
+    theta, norm, _ = oracle_net
+    m = _gpu_net(theta, norm)
+    nf = m.get_normalization().astype(np.float64)
+    fields = inputs.make_state(kind, lx, ly, seed=seed)
+    with lb.Lattice(lx, ly, TAU, [torch.from_numpy(a).cuda() for a in fields], precision="f32s",
+                    layout=layout) as lat:
+        lat.set_surrogate(m, 1e9)
+        lat.step(1)
+        f = lat.get_populations()
+        got = torch.stack([f[:, x, y] for x, y in sites]).cpu().numpy()
+        nfb, ntot = lat.surrogate_counts()
+    assert (nfb, ntot) == (0, lx * ly)
+    w = consts["w"]
+
+    def collide(win):
+        g = _f32(win.reshape(37, -1).T - w)
+        out, _, _ = S.surrogate_collide(g, TAU, theta, nf, 1e9)
+        return (out + w).T.reshape(win.shape)
+
+    ref = np.stack([_window_step(fields, s, collide) for s in sites])
+    return np.max(np.abs(got - ref) / w)
+
+
+def test_learned_step_full_size_sampled(consts, oracle_net):
+    """2048 x 2048, CAoSoA, the persistent launch the benchmark times: corners,
+    edges (periodic wrap), tile seams and random sites."""
+    lx = ly = 2048
+    rng = np.random.default_rng(5)
+    sites = [(0, 0), (lx - 1, ly - 1), (0, ly - 1), (lx - 1, 0), (1024, 511), (1024, 512), (7, 1535),
+             (2000, 1536)] + [(int(x), int(y)) for x, y in rng.integers(0, 2048, size=(8, 2))]
+    assert _learned_sampled_parity(consts, oracle_net, lx, ly, "caosoa", "shear_wave", sites) <= 2e-3 / TAU
+
+
+@pytest.mark.parametrize("lx,ly,layout", [(3, 96, "aos"), (3, 96, "csoa"), (9, 608, "caosoa"), (9, 608, "soa")])
+def test_learned_step_ragged_tiles(consts, oracle_net, lx, ly, layout):
+    """Grids below one workgroup per XCD (3 rows) and rows of 608 sites (a
+    full 512-site tile and a ragged one), in every layout."""
+    sites = [(0, 0), (lx - 1, ly - 1), (lx // 2, ly // 2), (1, ly - 3), (lx - 1, 2)]
+    if ly > 512:
+        sites += [(2, 511), (2, 512), (lx - 2, 600)]
+    assert _learned_sampled_parity(consts, oracle_net, lx, ly, layout, "rayleigh_taylor", sites) <= 2e-3 / TAU
+
+
 def _window_step(fields, site, collide):
     """One step at `site` on its 7 x 7 dependency window with a given collide."""
     rho, ux, uy, T = fields
