@@ -217,28 +217,36 @@ def table1_variant(args, torch, lb, inputs):
 
 
 def energy_variant(args, torch, lb, fields, net):
-    """Energy on the GPU package's counter around synchronised runs of about
-    2 s each (2048 x 2048 shear wave): per lattice update of the fused step
-    for each form, and, as in the paper's energy figure, per iteration of
-    the separate propagate and collide kernels for each FP64 layout."""
+    """Package power on the GPU's energy counter while a kernel loop runs
+    (2048 x 2048 shear wave, about 3 s per loop), times the loop's GPU time:
+    energy per lattice update of the fused step for each form and, as in the
+    paper's energy figure, energy per iteration of the separate propagate
+    and collide kernels for each FP64 layout."""
     from paper_1804_01918_amd.energy import EnergyMeter
     meter = EnergyMeter(0)
-    out = {"available": meter.available, "reason": meter.reason or None, "fused_step": {},
-           "f64_split_kernels_by_layout": {}}
+    out = {"available": meter.available, "reason": meter.reason or None,
+           "method": "average package power between counter refreshes seen while the loop ran x GPU time per call",
+           "fused_step": {}, "f64_split_kernels_by_layout": {}}
     if not meter.available:
         return out
 
-    def run_for(lat, fn, target_s=2.0):
+    def run_for(lat, fn, target_s):
         t = time_calls(lat, torch, fn, 20) / 20
         n = max(50, int(target_s / max(t, 1e-6)))
+        start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
 
-        def go():
+        def launch():
+            start.record(lat.stream)
             for _ in range(n):
                 fn()
-            torch.cuda.synchronize()
+            stop.record(lat.stream)
 
-        joules, dt = meter.measure(go)
-        return n, joules, dt
+        watts, span, refreshes = meter.power_during(launch, stop.query)
+        stop.synchronize()
+        per_call = start.elapsed_time(stop) / 1e3 / n
+        return {"calls": n, "gpu_s_per_call": per_call, "avg_watts": watts, "sampled_s": span,
+                "counter_refreshes": refreshes, "J_per_call": watts * per_call if watts is not None else None}
 
     forms = [("f64", None), ("f32s", None), ("f16s", None)] + ([("f32s", net)] if net is not None else [])
     for prec, nn in forms:
@@ -246,22 +254,16 @@ def energy_variant(args, torch, lb, fields, net):
         if nn is not None:
             lat.set_surrogate(nn, THRESHOLD)
         lat.step(args.warmup)
-        n, joules, dt = run_for(lat, lambda: lat.step(1))
-        key = ("learned_" if nn is not None else "") + f"{prec}_caosoa"
-        out["fused_step"][key] = {"steps": n, "seconds": dt, "joules": joules, "avg_watts": joules / dt,
-                                  "nJ_per_lattice_update": joules / (LX * LY * n) * 1e9,
-                                  "mlups": LX * LY * n / dt / 1e6}
+        r = run_for(lat, lambda: lat.step(1), 3.0)
+        r["nJ_per_lattice_update"] = r["J_per_call"] / (LX * LY) * 1e9 if r["J_per_call"] is not None else None
+        out["fused_step"][("learned_" if nn is not None else "") + f"{prec}_caosoa"] = r
         lat.close()
         del lat
         torch.cuda.empty_cache()
     for layout in ("aos", "soa", "csoa", "caosoa"):
         lat = lb.Lattice(LX, LY, TAU, fields, precision="f64", layout=layout)
-        rec = {}
-        for kname, fn in (("propagate", lat.propagate), ("collide", lat.collide)):
-            n, joules, dt = run_for(lat, fn, 1.0)
-            rec[kname] = {"calls": n, "ms_per_call": dt / n * 1e3, "J_per_iteration": joules / n,
-                          "avg_watts": joules / dt}
-        out["f64_split_kernels_by_layout"][layout] = rec
+        out["f64_split_kernels_by_layout"][layout] = {
+            "propagate": run_for(lat, lat.propagate, 2.0), "collide": run_for(lat, lat.collide, 2.0)}
         lat.close()
         del lat
         torch.cuda.empty_cache()

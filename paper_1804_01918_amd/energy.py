@@ -1,17 +1,26 @@
-"""GPU energy around a timed region, from the accumulated-energy counter that
-the AMD SMI library exposes for the device (read only).
+"""GPU energy from the accumulated-energy counter that the AMD SMI library
+exposes for the device package (read only).
 
 The paper's second figure of merit is energy to solution (its Section 5,
-Fig. 4); here the counterpart is the energy per lattice update of the fused
-step on the GPU package, read before and after a synchronised region.
+Fig. 4). Here the counterpart is the average package power while a kernel
+loop runs, times the loop's GPU time: energy per lattice update or per
+kernel call.
+
+The counter is refreshed by the firmware at its own interval, so a read
+just before and just after a short region can both return stale samples.
+The meter therefore enqueues the work, polls the counter while the GPU is
+busy, and takes the power between the first and the last refresh it sees
+inside the run (both taken while the work was executing).
 """
 from __future__ import annotations
 
+import time
+
 
 class EnergyMeter:
-    """Reads the energy counter of the GPU that torch calls `device`,
-    matched by PCI bus id. `available` is False (and `reason` says why) when
-    the SMI library or the counter cannot be used; measurements are then None."""
+    """Energy counter of the GPU that torch calls `device`, matched by PCI id.
+    `available` is False (and `reason` says why) when the SMI library or the
+    counter cannot be used."""
 
     def __init__(self, device: int = 0):
         self.available = False
@@ -26,10 +35,8 @@ class EnergyMeter:
             amdsmi.amdsmi_init()
             self._smi = amdsmi
             for h in amdsmi.amdsmi_get_processor_handles():
-                bdf = amdsmi.amdsmi_get_gpu_device_bdf(h)  # "dddd:bb:dd.f"
-                dom, bus, rest = bdf.split(":")
-                dev = rest.split(".")[0]
-                if (int(dom, 16), int(bus, 16), int(dev, 16)) == want:
+                dom, bus, rest = amdsmi.amdsmi_get_gpu_device_bdf(h).split(":")  # "dddd:bb:dd.f"
+                if (int(dom, 16), int(bus, 16), int(rest.split(".")[0], 16)) == want:
                     self._h = h
                     break
             if self._h is None:
@@ -40,22 +47,38 @@ class EnergyMeter:
         except Exception as e:  # no SMI library, no permission, no counter
             self.reason = f"{type(e).__name__}: {e}"
 
-    def _read(self) -> float:
-        """Accumulated energy in joules."""
+    def _read(self):
+        """(joules accumulated, counter timestamp)."""
         r = self._smi.amdsmi_get_energy_count(self._h)
-        return r["energy_accumulator"] * r["counter_resolution"] * 1e-6
+        return r["energy_accumulator"] * r["counter_resolution"] * 1e-6, r["timestamp"]
 
-    def measure(self, fn):
-        """Run fn() (which must synchronise the GPU before returning) and
-        return (joules, seconds), or (None, seconds) without a counter."""
-        import time
-        e0 = self._read() if self.available else None
-        t0 = time.perf_counter()
-        fn()
-        dt = time.perf_counter() - t0
-        if e0 is None:
-            return None, dt
-        return self._read() - e0, dt
+    def power_during(self, launch, done, poll_s: float = 0.001):
+        """Enqueue GPU work with launch() (asynchronous) and poll until done()
+        is true. Returns (average watts between the first and the last counter
+        refresh seen while the work ran, seconds between them, refreshes seen),
+        or (None, 0.0, n) if fewer than two refreshes fell inside the run."""
+        if not self.available:
+            launch()
+            while not done():
+                time.sleep(poll_s)
+            return None, 0.0, 0
+        _, ts = self._read()
+        launch()
+        first = last = None
+        n = 0
+        while not done():
+            e, t = self._read()
+            if t != ts:
+                ts = t
+                n += 1
+                now = time.perf_counter()
+                if first is None:
+                    first = (e, now)
+                last = (e, now)
+            time.sleep(poll_s)
+        if first is None or last is None or last[1] <= first[1]:
+            return None, 0.0, n
+        return (last[0] - first[0]) / (last[1] - first[1]), last[1] - first[1], n
 
     def close(self):
         if self._smi is not None:

@@ -244,13 +244,16 @@ def test_learned_step_full_size_sampled(consts, oracle_net):
     assert _learned_sampled_parity(consts, oracle_net, lx, ly, "caosoa", "shear_wave", sites) <= 2e-3 / TAU
 
 
-@pytest.mark.parametrize("lx,ly,layout", [(3, 96, "aos"), (3, 96, "csoa"), (9, 608, "caosoa"), (9, 608, "soa")])
+@pytest.mark.parametrize("lx,ly,layout", [(1, 1, "soa"), (1, 5, "aos"), (3, 96, "aos"), (3, 96, "csoa"),
+                                          (9, 608, "caosoa"), (9, 608, "soa")])
 def test_learned_step_ragged_tiles(consts, oracle_net, lx, ly, layout):
-    """Grids below one workgroup per XCD (3 rows) and rows of 608 sites (a
-    full 512-site tile and a ragged one), in every layout."""
+    """The 1 x 1 lattice (every population its own neighbour), grids below
+    one workgroup per XCD (1 or 3 rows) and rows of 608 sites (a full
+    512-site tile and a ragged one), in every layout."""
     sites = [(0, 0), (lx - 1, ly - 1), (lx // 2, ly // 2), (1, ly - 3), (lx - 1, 2)]
     if ly > 512:
         sites += [(2, 511), (2, 512), (lx - 2, 600)]
+    sites = sorted({(x % lx, y % ly) for x, y in sites})
     assert _learned_sampled_parity(consts, oracle_net, lx, ly, layout, "rayleigh_taylor", sites) <= 2e-3 / TAU
 
 
