@@ -225,7 +225,8 @@ def energy_variant(args, torch, lb, fields, net):
     from paper_1804_01918_amd.energy import EnergyMeter
     meter = EnergyMeter(0)
     out = {"available": meter.available, "reason": meter.reason or None,
-           "method": "average package power between counter refreshes seen while the loop ran x GPU time per call",
+           "method": "package power between energy-counter refreshes (about 1 s apart) inside the loop, "
+                     "times GPU time per call",
            "fused_step": {}, "f64_split_kernels_by_layout": {}}
     if not meter.available:
         return out
@@ -236,13 +237,21 @@ def energy_variant(args, torch, lb, fields, net):
         start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         torch.cuda.synchronize()
 
-        def launch():
-            start.record(lat.stream)
-            for _ in range(n):
-                fn()
-            stop.record(lat.stream)
+        chunk = 10
+        nchunks = (n + chunk - 1) // chunk
+        n = nchunks * chunk
+        state = {"i": 0}
 
-        watts, span, refreshes = meter.power_during(launch, stop.query)
+        def launch_chunk():
+            if state["i"] == 0:
+                start.record(lat.stream)
+            for _ in range(chunk):
+                fn()
+            state["i"] += 1
+            if state["i"] == nchunks:
+                stop.record(lat.stream)
+
+        watts, span, refreshes = meter.power_during(launch_chunk, nchunks, stop.query)
         stop.synchronize()
         per_call = start.elapsed_time(stop) / 1e3 / n
         return {"calls": n, "gpu_s_per_call": per_call, "avg_watts": watts, "sampled_s": span,
@@ -254,7 +263,7 @@ def energy_variant(args, torch, lb, fields, net):
         if nn is not None:
             lat.set_surrogate(nn, THRESHOLD)
         lat.step(args.warmup)
-        r = run_for(lat, lambda: lat.step(1), 3.0)
+        r = run_for(lat, lambda: lat.step(1), 3.5)
         r["nJ_per_lattice_update"] = r["J_per_call"] / (LX * LY) * 1e9 if r["J_per_call"] is not None else None
         out["fused_step"][("learned_" if nn is not None else "") + f"{prec}_caosoa"] = r
         lat.close()
@@ -263,7 +272,7 @@ def energy_variant(args, torch, lb, fields, net):
     for layout in ("aos", "soa", "csoa", "caosoa"):
         lat = lb.Lattice(LX, LY, TAU, fields, precision="f64", layout=layout)
         out["f64_split_kernels_by_layout"][layout] = {
-            "propagate": run_for(lat, lat.propagate, 2.0), "collide": run_for(lat, lat.collide, 2.0)}
+            "propagate": run_for(lat, lat.propagate, 2.5), "collide": run_for(lat, lat.collide, 2.5)}
         lat.close()
         del lat
         torch.cuda.empty_cache()

@@ -6,11 +6,12 @@ Fig. 4). Here the counterpart is the average package power while a kernel
 loop runs, times the loop's GPU time: energy per lattice update or per
 kernel call.
 
-The counter is refreshed by the firmware at its own interval, so a read
-just before and just after a short region can both return stale samples.
-The meter therefore enqueues the work, polls the counter while the GPU is
-busy, and takes the power between the first and the last refresh it sees
-inside the run (both taken while the work was executing).
+The counter is refreshed by the firmware at its own interval (about once a
+second, each value stamped with the firmware's time), so a read just before
+and just after a short region can both return stale samples. The meter
+therefore enqueues the work, polls the counter while the GPU is busy, and
+takes the power between the first and the last refresh it sees inside the
+run, on the counter's own timestamps.
 """
 from __future__ import annotations
 
@@ -52,33 +53,40 @@ class EnergyMeter:
         r = self._smi.amdsmi_get_energy_count(self._h)
         return r["energy_accumulator"] * r["counter_resolution"] * 1e-6, r["timestamp"]
 
-    def power_during(self, launch, done, poll_s: float = 0.001):
-        """Enqueue GPU work with launch() (asynchronous) and poll until done()
-        is true. Returns (average watts between the first and the last counter
-        refresh seen while the work ran, seconds between them, refreshes seen),
-        or (None, 0.0, n) if fewer than two refreshes fell inside the run."""
+    def power_during(self, launch_chunk, nchunks: int, done, poll_s: float = 0.001):
+        """Enqueue GPU work as nchunks calls of launch_chunk() (asynchronous;
+        the counter is polled between chunks, since enqueueing blocks once
+        the queue is full) and poll until done() is true. Returns (average
+        watts between the first and the last counter refresh seen while the
+        work ran, seconds between them on the counter's clock, refreshes
+        seen), or (None, 0.0, n) with fewer than two refreshes in the run."""
         if not self.available:
-            launch()
+            for _ in range(nchunks):
+                launch_chunk()
             while not done():
                 time.sleep(poll_s)
             return None, 0.0, 0
         _, ts = self._read()
-        launch()
-        first = last = None
-        n = 0
-        while not done():
+        samples = []
+
+        def poll():
+            nonlocal ts
             e, t = self._read()
             if t != ts:
                 ts = t
-                n += 1
-                now = time.perf_counter()
-                if first is None:
-                    first = (e, now)
-                last = (e, now)
+                samples.append((e, t))
+
+        for _ in range(nchunks):
+            launch_chunk()
+            poll()
+        while not done():
+            poll()
             time.sleep(poll_s)
-        if first is None or last is None or last[1] <= first[1]:
-            return None, 0.0, n
-        return (last[0] - first[0]) / (last[1] - first[1]), last[1] - first[1], n
+        if len(samples) < 2:
+            return None, 0.0, len(samples)
+        (e0, t0), (e1, t1) = samples[0], samples[-1]
+        span = (t1 - t0) * 1e-9  # counter timestamps are in ns
+        return (e1 - e0) / span, span, len(samples)
 
     def close(self):
         if self._smi is not None:

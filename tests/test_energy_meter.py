@@ -10,6 +10,6 @@ def test_meter_without_counter_reports_reason_and_runs_work():
         return
     assert m.reason
     ran = []
-    watts, span, n = m.power_during(lambda: ran.append(1), lambda: True)
-    assert ran == [1] and watts is None and span == 0.0 and n == 0
+    watts, span, n = m.power_during(lambda: ran.append(1), 3, lambda: True)
+    assert ran == [1, 1, 1] and watts is None and span == 0.0 and n == 0
     m.close()
