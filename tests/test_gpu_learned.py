@@ -330,6 +330,29 @@ def test_learned_conserves_mass_momentum_energy(consts, oracle_net):
     assert np.all(np.abs(a1 - a0) <= n * 2.0 ** -24 * scale * 8), (a1 - a0)
 
 
+def test_learned_fused_audit_matches_standalone(oracle_net):
+    """The FP64 audit fused into the learned step (one partial per persistent
+    workgroup) equals the standalone audit of the same state up to the
+    summation order: a missing or repeated partial would be off by about a
+    tile's worth of mass (~1), far above the bound."""
+    theta, norm, _ = oracle_net
+    m = _gpu_net(theta, norm)
+    lx, ly = 64, 1024
+    rho, ux, uy, T = inputs.rayleigh_taylor(lx, ly, seed=4)
+    T = T.copy()
+    T[:2, :] = 1.25  # outside the training box: these sites take the plain collide
+    fields = (rho, ux, uy, T)
+    totals = []
+    for audit in (True, False):
+        with lb.Lattice(lx, ly, TAU, fields, precision="f32s", layout="caosoa", audit=audit) as lat:
+            lat.set_surrogate(m, 1e9)
+            lat.step(3)
+            totals.append(lat.audit())
+            nfb, ntot = lat.surrogate_counts()
+            assert ntot == 3 * lx * ly and 0 < nfb < ntot  # both branches of the kernel ran
+    assert np.allclose(totals[0], totals[1], rtol=1e-13, atol=1e-9), totals
+
+
 def test_set_surrogate_rejects_other_precisions(oracle_net):
     theta, norm, _ = oracle_net
     m = _gpu_net(theta, norm)
