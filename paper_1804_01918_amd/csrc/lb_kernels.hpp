@@ -144,8 +144,9 @@ __global__ __launch_bounds__(BLOCK) void k_propagate(const typename P::Word* __r
     W w[Q];
 #pragma unroll
     for (int p = 0; p < Q; ++p) w[p] = ld_stream<W, L::stream_loads>(st.src(src, p, g));
+    // 2-byte words are stored without the streaming hint (see PrecF16S::store)
 #pragma unroll
-    for (int p = 0; p < Q; ++p) st_stream<W, L::stream_stores>(st.own(dst, p, g), w[p]);
+    for (int p = 0; p < Q; ++p) st_stream<W, L::stream_stores && (sizeof(W) > 2)>(st.own(dst, p, g), w[p]);
 }
 
 // Collide in place on the current buffer.
