@@ -408,7 +408,9 @@ def main():
                 "mlups": m, "ms_per_step": dtv / args.steps * 1e3,
                 "hbm_frac": m * 1e6 * bytes_per_site(prec[:3]) / (HBM_PEAK_GBS * 1e9),
                 "error_vs_f64_after_steps": args.steps + args.warmup,
-                "field_error_vs_f64": field_errors(ref_mom, mom)}
+                "field_error_vs_f64": field_errors(ref_mom, mom),
+                "hbm_traffic_bytes_per_launch": traffic_entry(f"k_step_{prec}_caosoa_2048x2048", nsites),
+                "algorithmic_bytes_per_launch": bytes_per_site(prec[:3]) * nsites}
         for layout in ("soa", "aos", "csoa"):
             dtv, _ = run("f64", layout, vs, args.warmup)
             m = nsites * vs / dtv / 1e6
