@@ -87,9 +87,10 @@ def copy_bandwidth(torch, lb, nbytes: int, reps: int = 20) -> float:
     return 2 * nbytes / dt / 1e9
 
 
-def traffic_entry(kernel: str, per_launch_sites: int):
-    """HBM bytes per launch from the committed rocprofv3 counter summary, if
-    it was taken on the current kernel sources; else None."""
+def traffic_entry(kernel: str, per_launch_sites: int, field: str = "hbm_bytes_per_launch"):
+    """A figure (HBM bytes per launch by default) from the committed
+    rocprofv3 counter summary, if it was taken on the current kernel
+    sources; else None."""
     from paper_1804_01918_amd.profsummary import source_digest
     if not os.path.exists(PROFILE_TRAFFIC):
         return None
@@ -100,7 +101,7 @@ def traffic_entry(kernel: str, per_launch_sites: int):
         return None
     if k.get("source_digest") != source_digest(k["source_files"]):
         return None
-    return k.get("hbm_bytes_per_launch")
+    return k.get(field)
 
 
 def cpu_baseline(seconds_target: float = 12.0):
@@ -395,8 +396,14 @@ def main():
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                      "kernel": "k_step<PrecF64, Layout<CAoSoA>> (fused propagate+collide)",
                      "algorithmic_bytes_per_site": bytes_per_site("f64", fused=True)},
+        "collide_vector_flops": None,
     }
 
+    fps = traffic_entry("k_step_f64_caosoa_2048x2048", nsites, "vector_flops_per_site")
+    if fps:
+        tf = fps * nsites / t_launch / 1e12
+        out["collide_vector_flops"] = {"flops_per_site": fps, "achieved_tflops": tf, "fp64_vector_peak_tflops": 78.6,
+                                       "frac": tf / 78.6, "source": "SQ_INSTS_VALU_{FMA,MUL,ADD,TRANS}_F64 counters"}
     if not args.no_variants:
         variants = {}
         vs = args.variant_steps

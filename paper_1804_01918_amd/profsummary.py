@@ -134,9 +134,13 @@ def main():
             lines.append(f"| {cname} | {v:.4g} | {64 * v / a.sites:.1f} lane-ops |")
         lines += ["", f"Counted vector flops (FMA = 2): {flops / a.sites:.0f} per site, "
                       f"{flops / (avg_us * 1e-6) / 1e12:.2f} TFLOP/s at the traced launch time.", ""]
+        valu_flops_per_site = flops / a.sites
+    else:
+        valu_flops_per_site = None
 
     entry = {"kernel": kname, "sites": a.sites, "avg_launch_us": avg_us,
-             "algorithmic_bytes_per_launch": a.alg_bytes, "source_files": list(files), "source_digest": digest}
+             "algorithmic_bytes_per_launch": a.alg_bytes, "source_files": list(files), "source_digest": digest,
+             "vector_flops_per_site": valu_flops_per_site}
     if a.fetch and a.write and a.copy_fetch and a.copy_write and a.copy_bytes:
         _, fk = _pick(counter_per_dispatch(a.fetch, "FETCH_SIZE"), a.match)
         _, wk = _pick(counter_per_dispatch(a.write, "WRITE_SIZE"), a.match)
