@@ -62,10 +62,11 @@ def test_2048_sampled_parity(consts, prec, kind):
         assert err <= (n + 1) * EPS[prec] * A * 4, (err, A)
 
 
-@pytest.mark.parametrize("prec", ["f64", "f32s"])
+@pytest.mark.parametrize("prec", ["f64", "f32s", "f16s"])
 def test_8192_sampled_parity(consts, prec):
-    """Largest workload size (8192 x 8192, about 20 GB of FP32 populations
-    or 40 GB of FP64), one step from the Rayleigh-Taylor-like state."""
+    """Largest workload size (8192 x 8192, about 40 GB of FP64 populations,
+    20 GB of FP32, 10 GB of FP16), one step from the Rayleigh-Taylor-like
+    state."""
     L, n, tau = 8192, 1, 0.8
     fields = inputs.rayleigh_taylor(L, L, seed=0)
     sites = _sample_sites(L, L, 48, seed=6)

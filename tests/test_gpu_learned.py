@@ -234,14 +234,16 @@ def _learned_sampled_parity(consts, oracle_net, lx, ly, layout, kind, sites, see
     return np.max(np.abs(got - ref) / w)
 
 
-def test_learned_step_full_size_sampled(consts, oracle_net):
-    """2048 x 2048, CAoSoA, the persistent launch the benchmark times: corners,
-    edges (periodic wrap), tile seams and random sites."""
-    lx = ly = 2048
+@pytest.mark.parametrize("L,kind", [(2048, "shear_wave"), (8192, "rayleigh_taylor")])
+def test_learned_step_full_size_sampled(consts, oracle_net, L, kind):
+    """2048 x 2048 and 8192 x 8192, CAoSoA, the persistent launch the
+    benchmark times: corners, edges (periodic wrap), tile seams and random
+    sites."""
+    lx = ly = L
     rng = np.random.default_rng(5)
-    sites = [(0, 0), (lx - 1, ly - 1), (0, ly - 1), (lx - 1, 0), (1024, 511), (1024, 512), (7, 1535),
-             (2000, 1536)] + [(int(x), int(y)) for x, y in rng.integers(0, 2048, size=(8, 2))]
-    assert _learned_sampled_parity(consts, oracle_net, lx, ly, "caosoa", "shear_wave", sites) <= 2e-3 / TAU
+    sites = [(0, 0), (lx - 1, ly - 1), (0, ly - 1), (lx - 1, 0), (L // 2, 511), (L // 2, 512), (7, L - 513),
+             (L - 48, L // 2)] + [(int(x), int(y)) for x, y in rng.integers(0, L, size=(8, 2))]
+    assert _learned_sampled_parity(consts, oracle_net, lx, ly, "caosoa", kind, sites) <= 2e-3 / TAU
 
 
 @pytest.mark.parametrize("lx,ly,layout", [(1, 1, "soa"), (1, 5, "aos"), (3, 96, "aos"), (3, 96, "csoa"),
