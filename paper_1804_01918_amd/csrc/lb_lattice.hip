@@ -399,6 +399,8 @@ int lb_set_surrogate(lb_ctx* c, const lb_mlp* m, double threshold)
         return fail(c, LB_EUNSUPPORTED, "lb_set_surrogate: the learned collide needs FP32-shifted populations");
     if (!(threshold >= 0.0) || !std::isfinite(threshold))
         return fail(c, LB_EINVAL, "lb_set_surrogate: threshold %g must be finite and >= 0", threshold);
+    if ((int64_t)c->geo.lx * c->geo.ly > (int64_t)UINT32_MAX)
+        return fail(c, LB_EINVAL, "lb_set_surrogate: the learned collide takes lattices of at most 2^32 - 1 sites");
     int dev = 0, ncu = 0;
     if (hipGetDevice(&dev) != hipSuccess ||
         hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || ncu < 1)

@@ -8,7 +8,9 @@
 // of one lattice row; the tiles of an XCD are contiguous). Each wavefront
 // stages its 64 sites' inputs in its own LDS rows, runs the network, then
 // gathers the populations a second time (cache hits) for the projection,
-// the fallback verdict and the relaxation.
+// the fallback verdict and the relaxation. Sites that fall back are queued
+// per wavefront in LDS and collided 64 at a time with the plain FP32 collide,
+// so that a few fallback lanes do not hold a whole wavefront in it.
 #pragma once
 
 #include "lb_kernels.hpp"
@@ -19,11 +21,64 @@ namespace d2q37 {
 constexpr int LBLOCK = 512;
 constexpr int LWAVES = LBLOCK / 64;
 
+constexpr int FQ = 128;  // fallback queue of a wavefront: < 64 waiting + one tile's 64
+
 struct LearnedLds {
     mlp::SharedWeights w;
     uint16_t X[LWAVES][mlp::WAVE_LDS_BYTES / 2];
+    uint32_t fq[LWAVES][FQ];  // queued fallback sites, x * LY + r (r: slot in row x)
     double red[LWAVES][4];
 };
+static_assert(sizeof(LearnedLds) <= 160 * 1024, "the learned kernels' LDS must fit one compute unit");
+
+// Plain FP32 collide of the queued fallback sites q[0..n), n <= 64, one per
+// lane: populations gathered from src (pulled, or the site's own with
+// INPLACE), result stored at the site in dst. Every lane must call it.
+template <class L, bool COMP, bool AUDIT, bool INPLACE>
+__device__ inline void fallback_batch(const uint32_t* q, int n, const float* src, float* dst, const Geo& g, float om,
+                                      double (&acc)[4])
+{
+    using P = PrecF32S;
+    constexpr int VL = vl_of<P>();
+    const int lane = mlp::lane_id();
+    const bool valid = lane < n;
+    const uint32_t e = q[valid ? lane : 0];
+    const int fx = (int)(e / (uint32_t)g.ly), fr = (int)(e - (uint32_t)fx * (uint32_t)g.ly);
+    Stencil<L, float, VL> st;
+    st.setup(fx, fr, g);
+    float v[Q];
+#pragma unroll
+    for (int p = 0; p < Q; ++p)
+        v[p] = P::template load<L::stream_loads>(INPLACE ? st.own(src, p, g) : st.src(src, p, g), p);
+    if (valid) {
+        double d[Q];
+        collide_site<P, COMP>(v, om, [&](int p, float res) {
+            P::template store<L::stream_stores>(st.own(dst, p, g), p, res);
+            if constexpr (AUDIT) d[p] = (double)res;
+        });
+        if constexpr (AUDIT) audit_site(d, acc);
+    }
+}
+
+// Queue this tile's fallback lanes (mask m of lanes with fb set) and, once 64
+// are waiting, collide them. qn: entries waiting (wavefront-uniform).
+template <class L, bool COMP, bool AUDIT, bool INPLACE>
+__device__ inline void queue_fallback(uint32_t* q, int& qn, uint64_t m, bool fb, uint32_t site, const float* src,
+                                      float* dst, const Geo& g, float om, double (&acc)[4])
+{
+    if (m == 0) return;
+    const int lane = mlp::lane_id();
+    if (fb) q[qn + __popcll(m & ((1ull << lane) - 1ull))] = site;
+    qn += __popcll(m);
+    if (qn >= 64) {
+        mlp::wave_sync();
+        fallback_batch<L, COMP, AUDIT, INPLACE>(q, 64, src, dst, g, om, acc);
+        const int rest = qn - 64;
+        mlp::wave_sync();
+        if (lane < rest) q[lane] = q[64 + lane];
+        qn = rest;
+    }
+}
 
 // Tiles [first, end) with stride step visited by this workgroup.
 struct TileWalk {
@@ -84,6 +139,8 @@ __global__ __launch_bounds__(LBLOCK) __attribute__((amdgpu_waves_per_eu(2, 2))) 
     const mlp::Net net = mlp::share_weights<LBLOCK>(gnet, S.w);
     __syncthreads();
     uint16_t* X = S.X[threadIdx.x >> 6];
+    uint32_t* q = S.fq[threadIdx.x >> 6];
+    int qn = 0;
     const float om = (float)omega;
     double acc[4] = {0.0, 0.0, 0.0, 0.0};
     unsigned long long nfb = 0, nact = 0;
@@ -111,24 +168,24 @@ __global__ __launch_bounds__(LBLOCK) __attribute__((amdgpu_waves_per_eu(2, 2))) 
         float gh[Q];
         const mlp::Verdict vd = mlp::learned_equilibrium(v, net, X, threshold, gh);
         const bool fb = active && vd.fallback;
-        if (active) {
+        if (active && !fb) {
             double d[Q];
-            auto store = [&](int p, float res) {
+#pragma unroll
+            for (int p = 0; p < Q; ++p) {
+                const float res = __builtin_fmaf(om, gh[p] - v[p], v[p]);
                 P::template store<L::stream_stores>(st.own(dst, p, g), p, res);
                 if constexpr (AUDIT) d[p] = (double)res;
-            };
-            if (fb) {
-                collide_site<P, COMP>(v, om, store);
-            } else {
-#pragma unroll
-                for (int p = 0; p < Q; ++p) store(p, __builtin_fmaf(om, gh[p] - v[p], v[p]));
             }
             if constexpr (AUDIT) audit_site(d, acc);
         }
-        nfb += __popcll(__ballot(fb));
+        const uint64_t m = __ballot(fb);
+        nfb += __popcll(m);
         nact += __popcll(__ballot(active));
+        queue_fallback<L, COMP, AUDIT, false>(q, qn, m, fb, (uint32_t)xrow * (uint32_t)g.ly + (uint32_t)r, src, dst,
+                                              g, om, acc);
         mlp::wave_sync();  // the staged rows are reused by the next tile
     }
+    if (qn > 0) fallback_batch<L, COMP, AUDIT, false>(q, qn, src, dst, g, om, acc);
     finish_learned<AUDIT>(S, acc, nfb, nact, partials, counts);
 }
 
@@ -144,6 +201,8 @@ __global__ __launch_bounds__(LBLOCK) __attribute__((amdgpu_waves_per_eu(2, 2))) 
     const mlp::Net net = mlp::share_weights<LBLOCK>(gnet, S.w);
     __syncthreads();
     uint16_t* X = S.X[threadIdx.x >> 6];
+    uint32_t* q = S.fq[threadIdx.x >> 6];
+    int qn = 0;
     const float om = (float)omega;
     double acc[4] = {0.0, 0.0, 0.0, 0.0};
     unsigned long long nfb = 0, nact = 0;
@@ -169,19 +228,20 @@ __global__ __launch_bounds__(LBLOCK) __attribute__((amdgpu_waves_per_eu(2, 2))) 
         float gh[Q];
         const mlp::Verdict vd = mlp::learned_equilibrium(v, net, X, threshold, gh);
         const bool fb = active && vd.fallback;
-        if (active) {
-            auto store = [&](int p, float res) { P::template store<L::stream_stores>(st.own(buf, p, g), p, res); };
-            if (fb) {
-                collide_site<P, COMP>(v, om, store);
-            } else {
+        if (active && !fb) {
 #pragma unroll
-                for (int p = 0; p < Q; ++p) store(p, __builtin_fmaf(om, gh[p] - v[p], v[p]));
-            }
+            for (int p = 0; p < Q; ++p)
+                P::template store<L::stream_stores>(st.own(buf, p, g), p, __builtin_fmaf(om, gh[p] - v[p], v[p]));
         }
-        nfb += __popcll(__ballot(fb));
+        const uint64_t m = __ballot(fb);
+        nfb += __popcll(m);
         nact += __popcll(__ballot(active));
+        // a queued site is untouched until its batch runs: every site writes only itself
+        queue_fallback<L, COMP, false, true>(q, qn, m, fb, (uint32_t)xrow * (uint32_t)g.ly + (uint32_t)r, buf, buf, g,
+                                             om, acc);
         mlp::wave_sync();
     }
+    if (qn > 0) fallback_batch<L, COMP, false, true>(q, qn, buf, buf, g, om, acc);
     finish_learned<false>(S, acc, nfb, nact, nullptr, counts);
 }
 
