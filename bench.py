@@ -340,9 +340,10 @@ def main():
     nsites = LX * LY
     counts = {}
 
-    def run(prec, layout, steps, warmup, split=False, keep=False, state=None, net=None, threshold=THRESHOLD):
+    def run(prec, layout, steps, warmup, split=False, keep=False, state=None, net=None, threshold=THRESHOLD,
+            compensated=None):
         lx, ly, flds = state if state is not None else (LX, LY, fields)
-        lat = lb.Lattice(lx, ly, TAU, flds, precision=prec, layout=layout, audit=True)
+        lat = lb.Lattice(lx, ly, TAU, flds, precision=prec, layout=layout, audit=True, compensated=compensated)
         if net is not None:
             lat.set_surrogate(net, threshold)
         if split:
@@ -418,6 +419,13 @@ def main():
                 "field_error_vs_f64": field_errors(ref_mom, mom),
                 "hbm_traffic_bytes_per_launch": traffic_entry(f"k_step_{prec}_caosoa_2048x2048", nsites),
                 "algorithmic_bytes_per_launch": bytes_per_site(prec[:3]) * nsites}
+        # the same FP32 step with plain (uncompensated) moment sums
+        dtv, mom = run("f32s", "caosoa", args.steps, args.warmup, keep=True, compensated=False)
+        m = nsites * args.steps / dtv / 1e6
+        variants["f32s_caosoa_fused_uncompensated"] = {
+            "compensated_moment_sums": False, "mlups": m,
+            "hbm_frac": m * 1e6 * bytes_per_site("f32") / (HBM_PEAK_GBS * 1e9),
+            "error_vs_f64_after_steps": args.steps + args.warmup, "field_error_vs_f64": field_errors(ref_mom, mom)}
         for layout in ("soa", "aos", "csoa"):
             dtv, _ = run("f64", layout, vs, args.warmup)
             m = nsites * vs / dtv / 1e6
@@ -440,6 +448,8 @@ def main():
         for prec in ("f32s", "f16s"):
             _, mom = run(prec, "caosoa", args.steps, args.warmup, keep=True, state=rt)
             variants["rayleigh_taylor_2048"][f"{prec}_field_error_vs_f64"] = field_errors(rt_ref, mom)
+        _, mom = run("f32s", "caosoa", args.steps, args.warmup, keep=True, state=rt, compensated=False)
+        variants["rayleigh_taylor_2048"]["f32s_uncompensated_field_error_vs_f64"] = field_errors(rt_ref, mom)
         out["variants"] = variants
 
     if not args.no_learned:

@@ -125,23 +125,21 @@ __device__ inline void finish_learned(LearnedLds& S, double (&acc)[4], unsigned 
     }
 }
 
-// Fused step src -> dst with the learned collide; g.tpr counts 512-site
-// tiles per row here. With AUDIT, partials[4 * blockIdx.x ..] receive the
-// workgroup's FP64 sums.
-template <class L, bool COMP, bool AUDIT>
-__global__ __launch_bounds__(LBLOCK) __attribute__((amdgpu_waves_per_eu(2, 2))) void k_step_learned(
-    const float* __restrict__ src, float* __restrict__ dst, Geo g, double omega, mlp::Net gnet, float threshold,
-    double* __restrict__ partials, unsigned long long* __restrict__ counts)
+// The tile loop of both learned kernels. INPLACE: the collide of the
+// current buffer (src == dst, each site's own populations); otherwise the
+// fused step src -> dst (pulled populations). With AUDIT,
+// partials[4 * blockIdx.x ..] receive the workgroup's FP64 sums.
+template <class L, bool COMP, bool AUDIT, bool INPLACE>
+__device__ inline void learned_tiles(LearnedLds& S, const mlp::Net& gnet, const float* src, float* dst, const Geo& g,
+                                     float om, float threshold, double* partials, unsigned long long* counts)
 {
     using P = PrecF32S;
     constexpr int VL = vl_of<P>();
-    __shared__ LearnedLds S;
     const mlp::Net net = mlp::share_weights<LBLOCK>(gnet, S.w);
     __syncthreads();
     uint16_t* X = S.X[threadIdx.x >> 6];
     uint32_t* q = S.fq[threadIdx.x >> 6];
     int qn = 0;
-    const float om = (float)omega;
     double acc[4] = {0.0, 0.0, 0.0, 0.0};
     unsigned long long nfb = 0, nact = 0;
     const TileWalk tw = tile_walk((int64_t)g.lx * g.tpr);
@@ -153,18 +151,19 @@ __global__ __launch_bounds__(LBLOCK) __attribute__((amdgpu_waves_per_eu(2, 2))) 
         // no per-load predication) and store nothing
         Stencil<L, float, VL> st;
         st.setup(xrow, active ? r : g.ly - 1, g);
+        auto at = [&](int p) { return INPLACE ? st.own(src, p, g) : st.src(src, p, g); };
         // first gather: standardised network inputs (loads that keep the lines cached)
         {
             float in[Q];
 #pragma unroll
-            for (int p = 0; p < Q; ++p) in[p] = P::template load<false>(st.src(src, p, g), p);
+            for (int p = 0; p < Q; ++p) in[p] = P::template load<false>(at(p), p);
             mlp::stage_inputs(X, net, in);
         }
         mlp::network_outputs(net, X);
         // second gather: the populations for projection and relaxation
         float v[Q];
 #pragma unroll
-        for (int p = 0; p < Q; ++p) v[p] = P::template load<L::stream_loads>(st.src(src, p, g), p);
+        for (int p = 0; p < Q; ++p) v[p] = P::template load<L::stream_loads>(at(p), p);
         float gh[Q];
         const mlp::Verdict vd = mlp::learned_equilibrium(v, net, X, threshold, gh);
         const bool fb = active && vd.fallback;
@@ -181,12 +180,25 @@ __global__ __launch_bounds__(LBLOCK) __attribute__((amdgpu_waves_per_eu(2, 2))) 
         const uint64_t m = __ballot(fb);
         nfb += __popcll(m);
         nact += __popcll(__ballot(active));
-        queue_fallback<L, COMP, AUDIT, false>(q, qn, m, fb, (uint32_t)xrow * (uint32_t)g.ly + (uint32_t)r, src, dst,
-                                              g, om, acc);
+        // in place, a queued site stays untouched until its batch runs:
+        // every site writes only itself
+        queue_fallback<L, COMP, AUDIT, INPLACE>(q, qn, m, fb, (uint32_t)xrow * (uint32_t)g.ly + (uint32_t)r, src, dst,
+                                                g, om, acc);
         mlp::wave_sync();  // the staged rows are reused by the next tile
     }
-    if (qn > 0) fallback_batch<L, COMP, AUDIT, false>(q, qn, src, dst, g, om, acc);
+    if (qn > 0) fallback_batch<L, COMP, AUDIT, INPLACE>(q, qn, src, dst, g, om, acc);
     finish_learned<AUDIT>(S, acc, nfb, nact, partials, counts);
+}
+
+// Fused step src -> dst with the learned collide; g.tpr counts 512-site
+// tiles per row here.
+template <class L, bool COMP, bool AUDIT>
+__global__ __launch_bounds__(LBLOCK) __attribute__((amdgpu_waves_per_eu(2, 2))) void k_step_learned(
+    const float* __restrict__ src, float* __restrict__ dst, Geo g, double omega, mlp::Net gnet, float threshold,
+    double* __restrict__ partials, unsigned long long* __restrict__ counts)
+{
+    __shared__ LearnedLds S;
+    learned_tiles<L, COMP, AUDIT, false>(S, gnet, src, dst, g, (float)omega, threshold, partials, counts);
 }
 
 // In-place learned collide on the current buffer (same walk).
@@ -195,54 +207,8 @@ __global__ __launch_bounds__(LBLOCK) __attribute__((amdgpu_waves_per_eu(2, 2))) 
     float* __restrict__ buf, Geo g, double omega, mlp::Net gnet, float threshold,
     unsigned long long* __restrict__ counts)
 {
-    using P = PrecF32S;
-    constexpr int VL = vl_of<P>();
     __shared__ LearnedLds S;
-    const mlp::Net net = mlp::share_weights<LBLOCK>(gnet, S.w);
-    __syncthreads();
-    uint16_t* X = S.X[threadIdx.x >> 6];
-    uint32_t* q = S.fq[threadIdx.x >> 6];
-    int qn = 0;
-    const float om = (float)omega;
-    double acc[4] = {0.0, 0.0, 0.0, 0.0};
-    unsigned long long nfb = 0, nact = 0;
-    const TileWalk tw = tile_walk((int64_t)g.lx * g.tpr);
-    for (int64_t tile = tw.first; tile < tw.end; tile += tw.step) {
-        const int xrow = (int)(tile / g.tpr);
-        const int r = (int)(tile - (int64_t)xrow * g.tpr) * LBLOCK + (int)threadIdx.x;
-        const bool active = r < g.ly;
-        // lanes past the row end read the row's last site (valid addresses,
-        // no per-load predication) and store nothing
-        Stencil<L, float, VL> st;
-        st.setup(xrow, active ? r : g.ly - 1, g);
-        {
-            float in[Q];
-#pragma unroll
-            for (int p = 0; p < Q; ++p) in[p] = P::template load<false>(st.own(buf, p, g), p);
-            mlp::stage_inputs(X, net, in);
-        }
-        mlp::network_outputs(net, X);
-        float v[Q];
-#pragma unroll
-        for (int p = 0; p < Q; ++p) v[p] = P::template load<L::stream_loads>(st.own(buf, p, g), p);
-        float gh[Q];
-        const mlp::Verdict vd = mlp::learned_equilibrium(v, net, X, threshold, gh);
-        const bool fb = active && vd.fallback;
-        if (active && !fb) {
-#pragma unroll
-            for (int p = 0; p < Q; ++p)
-                P::template store<L::stream_stores>(st.own(buf, p, g), p, __builtin_fmaf(om, gh[p] - v[p], v[p]));
-        }
-        const uint64_t m = __ballot(fb);
-        nfb += __popcll(m);
-        nact += __popcll(__ballot(active));
-        // a queued site is untouched until its batch runs: every site writes only itself
-        queue_fallback<L, COMP, false, true>(q, qn, m, fb, (uint32_t)xrow * (uint32_t)g.ly + (uint32_t)r, buf, buf, g,
-                                             om, acc);
-        mlp::wave_sync();
-    }
-    if (qn > 0) fallback_batch<L, COMP, false, true>(q, qn, buf, buf, g, om, acc);
-    finish_learned<false>(S, acc, nfb, nact, nullptr, counts);
+    learned_tiles<L, COMP, false, true>(S, gnet, buf, buf, g, (float)omega, threshold, nullptr, counts);
 }
 
 }  // namespace d2q37
