@@ -434,6 +434,12 @@ def main():
             dtv, _ = run("f64", layout, vs, args.warmup, split=True)
             m = nsites * vs / dtv / 1e6
             variants[f"f64_{layout}_split"] = {"mlups": m, "hbm_frac": m * 1e6 * 1184 / (HBM_PEAK_GBS * 1e9)}
+        # spread of the headline: three more timed runs of the same workload
+        reps = []
+        for _ in range(3):
+            dtr, _ = run("f64", "caosoa", args.steps, args.warmup)
+            reps.append(nsites * args.steps / dtr / 1e6)
+        variants["f64_caosoa_fused_repeats_mlups"] = reps
         cb = copy_bandwidth(torch, lb, alg_bytes // 2)
         variants["copy_kernel_gbs"] = cb
         out["roofline"]["frac_of_copy"] = achieved / cb

@@ -139,6 +139,24 @@ def test_training_steps_match_oracle(oracle_net):
     assert d.max() <= 4 * lr
 
 
+def test_training_is_reproducible():
+    """Pair generation, standardisation and training use no floating-point
+    atomics: two runs from the same seeds give bit-identical parameters,
+    standardisation and loss history."""
+    out = []
+    for _ in range(2):
+        pre, post = lb.pairgen(1 << 16, 5, TAU)
+        m = lb.Mlp(2048)
+        m.fit_normalization(pre, post, TAU)
+        m.init(2)
+        losses = m.train(pre, post, TAU, 2048, 3, 2e-3, 9)
+        out.append((m.get_params(), m.get_normalization(), losses))
+        m.close()
+    assert np.array_equal(out[0][0], out[1][0])
+    assert np.array_equal(out[0][1], out[1][1])
+    assert np.array_equal(out[0][2], out[1][2])
+
+
 def test_learned_equilibrium_matches_oracle(consts, oracle_net):
     theta, norm, _ = oracle_net
     m = _gpu_net(theta, norm)
