@@ -133,6 +133,60 @@ def model_constants():
     return r.value, w, c
 
 
+# ---- the C-ABI calls under their own names (marshalling only) -----------------
+# ctx is the lb_ctx handle (ctypes.c_void_p); device arrays are torch CUDA
+# tensors (or raw device addresses as int). Errors raise LBError.
+
+def _ptr(a) -> int:
+    return a if isinstance(a, int) else a.data_ptr()
+
+
+def lb_buffer_bytes(lx: int, ly: int, precision: str = "f64", layout: str = "soa") -> int:
+    return lib().lb_buffer_bytes(lx, ly, PRECISIONS[precision], LAYOUTS[layout])
+
+
+def lb_scratch_bytes(lx: int, ly: int) -> int:
+    return lib().lb_scratch_bytes(lx, ly)
+
+
+def lb_init(cfg: Config, rho, ux, uy, T) -> ctypes.c_void_p:
+    ctx = ctypes.c_void_p()
+    _check(lib().lb_init(ctypes.byref(ctx), ctypes.byref(cfg), _ptr(rho), _ptr(ux), _ptr(uy), _ptr(T)), None,
+           "lb_init")
+    return ctx
+
+
+def lb_propagate(ctx):
+    _check(lib().lb_propagate(ctx), ctx, "lb_propagate")
+
+
+def lb_collide(ctx):
+    _check(lib().lb_collide(ctx), ctx, "lb_collide")
+
+
+def lb_step(ctx, nsteps: int = 1):
+    _check(lib().lb_step(ctx, int(nsteps)), ctx, "lb_step")
+
+
+def lb_moments(ctx, rho, ux, uy, T):
+    _check(lib().lb_moments(ctx, _ptr(rho), _ptr(ux), _ptr(uy), _ptr(T)), ctx, "lb_moments")
+
+
+def lb_audit(ctx) -> np.ndarray:
+    out = (ctypes.c_double * 4)()
+    rc = lib().lb_audit(ctx, out)
+    vals = np.array(list(out))
+    if rc == LB_ENONFINITE:
+        raise LBNonFinite(rc, lib().lb_last_error(ctx).decode(), vals)
+    _check(rc, ctx, "lb_audit")
+    return vals
+
+
+def lb_destroy(ctx):
+    if ctx is not None and ctx.value:
+        lib().lb_destroy(ctx)
+
+
 def _torch():
     import torch
     if not torch.cuda.is_available():
@@ -296,9 +350,8 @@ class Lattice:
         self.cfg.scratch, self.cfg.scratch_bytes = self.scratch.data_ptr(), sbytes
         self.cfg.stream = self.stream.cuda_stream
         fl = [self._field(a) for a in fields]
-        self._ctx = ctypes.c_void_p()
-        _check(lib().lb_init(ctypes.byref(self._ctx), ctypes.byref(self.cfg),
-                             *[a.data_ptr() for a in fl]), None, "lb_init")
+        self._ctx = None
+        self._ctx = lb_init(self.cfg, *fl)
         self._fields_keepalive = fl
 
     def _field(self, a):
@@ -318,19 +371,19 @@ class Lattice:
 
     # -- the method ---------------------------------------------------------
     def propagate(self):
-        _check(lib().lb_propagate(self.ctx), self.ctx, "lb_propagate")
+        lb_propagate(self.ctx)
 
     def collide(self):
-        _check(lib().lb_collide(self.ctx), self.ctx, "lb_collide")
+        lb_collide(self.ctx)
 
     def step(self, nsteps: int = 1):
-        _check(lib().lb_step(self.ctx, int(nsteps)), self.ctx, "lb_step")
+        lb_step(self.ctx, nsteps)
 
     # -- readouts -----------------------------------------------------------
     def moments(self):
         torch = _torch()
         out = [torch.empty((self.lx, self.ly), dtype=torch.float64, device=self.device) for _ in range(4)]
-        _check(lib().lb_moments(self.ctx, *[o.data_ptr() for o in out]), self.ctx, "lb_moments")
+        lb_moments(self.ctx, *out)
         return tuple(out)
 
     def get_populations(self):
@@ -350,13 +403,7 @@ class Lattice:
         self.stream.synchronize()
 
     def audit(self) -> np.ndarray:
-        out = (ctypes.c_double * 4)()
-        rc = lib().lb_audit(self.ctx, out)
-        vals = np.array(list(out))
-        if rc == LB_ENONFINITE:
-            raise LBNonFinite(rc, lib().lb_last_error(self.ctx).decode(), vals)
-        _check(rc, self.ctx, "lb_audit")
-        return vals
+        return lb_audit(self.ctx)
 
     def set_surrogate(self, mlp, threshold: float = 1e-3):
         """Collide with the network (FP32-shifted lattices); None restores the
@@ -384,8 +431,7 @@ class Lattice:
         self.bufs[self.current_buffer()].copy_(raw)
 
     def close(self):
-        if self._ctx is not None and self._ctx.value:
-            lib().lb_destroy(self._ctx)
+        lb_destroy(self._ctx)
         self._ctx = None
 
     def __del__(self):

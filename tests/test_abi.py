@@ -28,6 +28,16 @@ def test_header_declares_expected_entry_points():
 
 
 @pytest.mark.parametrize("name", declared_functions())
+def test_binding_knows_every_entry_point(name):
+    """Every declared call has a ctypes signature in the binding, and the
+    step calls are also Python functions of the same name."""
+    assert name in lb._SIGNATURES, name
+    if name in ("lb_buffer_bytes", "lb_scratch_bytes", "lb_init", "lb_propagate", "lb_collide", "lb_step",
+                "lb_moments", "lb_audit", "lb_destroy"):
+        assert callable(getattr(lb, name)), name
+
+
+@pytest.mark.parametrize("name", declared_functions())
 def test_library_exports(name):
     so = ctypes.CDLL(lb.LIB_PATH)
     assert hasattr(so, name), name
