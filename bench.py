@@ -292,6 +292,8 @@ def scale_variant(args, torch, inputs, run, counts, net):
     out["f64"] = {"mlups": n * n * steps / dt / 1e6}
     dt, mom = run("f32s", "caosoa", steps, warm, keep=True, state=state)
     out["f32s"] = {"mlups": n * n * steps / dt / 1e6, "field_error_vs_f64": field_errors(ref, mom)}
+    dt, mom = run("f16s", "caosoa", steps, warm, keep=True, state=state)
+    out["f16s"] = {"mlups": n * n * steps / dt / 1e6, "field_error_vs_f64": field_errors(ref, mom)}
     counts.clear()
     dt, mom = run("f32s", "caosoa", steps, warm, keep=True, state=state, net=net)
     out["learned_f32s"] = {"mlups": n * n * steps / dt / 1e6, "fallback_fraction": counts.get("fallback_fraction"),
