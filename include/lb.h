@@ -245,7 +245,13 @@ int lb_pairgen(float *pre, float *post, int64_t n, uint64_t seed, double tau, vo
 
 /* Use the network for the collide of an FP32-shifted lattice (fused step and
  * lb_collide); NULL returns to the plain collide. The network must outlive
- * its use. Sites with residual > threshold fall back to the plain collide. */
+ * its use. Sites with residual > threshold (or outside the training box)
+ * fall back to the plain FP32 collide; with threshold 0 every site does and
+ * the step equals the plain FP32 step bit for bit. Errors: LB_EUNSUPPORTED
+ * for FP64 or FP16 storage; LB_EINVAL for a negative or non-finite threshold
+ * or a lattice of more than 2^32 - 1 sites; LB_EDEVICE if the device cannot
+ * be queried. No device memory is allocated. (Not in the paper: the learned
+ * collide is an addition to its method.) */
 int lb_set_surrogate(lb_ctx *ctx, const lb_mlp *m, double threshold);
 
 /* {fallback sites, collided sites} accumulated by the learned collide since
