@@ -72,7 +72,9 @@ typedef enum { LB_FP64 = 0, LB_FP32_SHIFTED = 1, LB_FP16_SHIFTED = 2 } lb_precis
 typedef enum { LB_SOA = 0, LB_AOS = 1, LB_CSOA = 2, LB_CAOSOA = 3 } lb_layout;
 
 typedef struct {
-    int32_t lx, ly;       /* periodic extents, >= 1 each, lx*ly < 2^31 */
+    int32_t lx, ly;       /* periodic extents, >= 1 each, lx*ly < 2^31; one row of a
+                             population term at most 4 GiB: ly*37*elem <= 2^32 for
+                             AoS and CAoSoA, ly*elem <= 2^32 for SoA and CSoA */
     double tau;           /* BGK relaxation time in steps, > 0.5 */
     int32_t precision;    /* lb_precision */
     int32_t layout;       /* lb_layout */
@@ -87,16 +89,35 @@ typedef struct {
 
 typedef struct lb_ctx lb_ctx;
 
-/* Bytes of one population buffer; 0 if the combination is invalid. */
+/* Bytes of one population buffer (paper, Section 4: the lattice holds 37
+ * populations per site, in two copies; Fig. 2 gives the layouts): 37 * lx *
+ * ly elements rounded up to 256 bytes. Returns 0 if the combination is
+ * invalid: an extent < 1, lx * ly >= 2^31, an unknown precision or layout,
+ * ly not a multiple of VL for CSoA and CAoSoA, or a row whose bytes within
+ * one population term exceed 4 GiB (ly * 37 * elem for AoS and CAoSoA,
+ * ly * elem for SoA and CSoA; the kernels address a row with 32-bit byte
+ * offsets). Host only; never touches the device. */
 size_t lb_buffer_bytes(int32_t lx, int32_t ly, int32_t precision, int32_t layout);
 
-/* Bytes of scratch a context of this lattice needs (audit partial sums). */
+/* Bytes of scratch a context of this lattice needs: the FP64 partial sums of
+ * the audit (4 per 256-site row tile), its 4 totals and the two counters of
+ * the learned collide; 0 for an invalid extent. Host only. */
 size_t lb_scratch_bytes(int32_t lx, int32_t ly);
 
 /* Create a context and set the populations of buf[0] to the equilibrium of
- * the FP64 device fields rho, ux, uy, T ([lx][ly] each). On error *out is
- * NULL. Validates: extents, tau > 0.5, precision/layout, LY % VL for the
- * clustered layouts, non-NULL 256-byte-aligned buffers, scratch size. */
+ * the FP64 device fields rho, ux, uy, T ([lx][ly] each, thermal units; read
+ * only, may be freed once the stream has passed this call). The equilibrium
+ * is the model's (paper, Section 3: the D2Q37 equilibrium of density rho,
+ * velocity u and temperature T, with pressure p = rho T), in this build the
+ * fourth-order Hermite expansion of the Maxwellian on the 37-velocity
+ * quadrature. The context borrows cfg's buffers and stream until
+ * lb_destroy. On error *out is NULL and nothing was launched. Validates,
+ * before any device work: extents and the row-size limit of lb_config
+ * (LB_EINVAL / LB_EUNSUPPORTED), tau > 0.5 and finite (LB_EINVAL), the
+ * precision and layout (LB_EUNSUPPORTED), LY % VL for the clustered layouts
+ * (LB_EUNSUPPORTED), non-NULL, distinct, 256-byte-aligned buffers and
+ * scratch of at least lb_scratch_bytes() (LB_EINVAL), non-NULL fields
+ * (LB_EINVAL). LB_EDEVICE if the launch fails. */
 int lb_init(lb_ctx **out, const lb_config *cfg, const double *rho, const double *ux,
             const double *uy, const double *T);
 
@@ -109,28 +130,45 @@ int lb_propagate(lb_ctx *ctx);
  * relaxation f <- f - (f - f_eq)/tau, in place on the current buffer. */
 int lb_collide(lb_ctx *ctx);
 
-/* nsteps time steps, each propagate then collide fused in one kernel that
- * reads the current buffer and writes the other (ping-pong). Bit-identical
- * to nsteps x (lb_propagate; lb_collide). nsteps = 0 is a no-op. */
+/* nsteps time steps (paper, Section 3: a time step is propagate followed by
+ * collide; Section 4 and Listing 1: two copies of the lattice, one read and
+ * one written). Each step runs both in one kernel that pulls from the
+ * current buffer, collides in registers and writes the other buffer, which
+ * then becomes current (ping-pong). Bit-identical to nsteps x
+ * (lb_propagate; lb_collide). nsteps = 0 is a no-op; LB_EINVAL for a NULL
+ * context or nsteps < 0; LB_EDEVICE if a launch fails. Asynchronous. */
 int lb_step(lb_ctx *ctx, int32_t nsteps);
 
-/* Macroscopic fields of the current state, in FP64 (device [lx][ly] each):
- * rho = sum f, rho u = sum f xi, rho (|u|^2 + 2 T) = sum f |xi|^2. */
+/* Macroscopic fields of the current state (paper, Section 3: density,
+ * velocity and temperature of a site, the moments the collide relaxes
+ * around), in FP64 into caller-owned device arrays [lx][ly] each:
+ * rho = sum f, rho u = sum f xi, rho (|u|^2 + 2 T) = sum f |xi|^2, with
+ * xi = r c the thermal velocities. LB_EINVAL for a NULL context or array.
+ * Asynchronous. */
 int lb_moments(lb_ctx *ctx, double *rho, double *ux, double *uy, double *T);
 
-/* Current populations in the canonical FP64 layout (device [37][lx][ly]);
- * shifted storage is returned as f = w_p + g. */
+/* Current populations in the canonical FP64 layout (device [37][lx][ly],
+ * caller-owned; the [p][x][y] order of Listing 1 in Section 4, converted from
+ * the storage layout of Fig. 2). Shifted storage is returned as f = w_p + g
+ * (exact). LB_EINVAL for a NULL context or array. Asynchronous. */
 int lb_get_populations(lb_ctx *ctx, double *f);
 
-/* Replace the current populations from canonical FP64 (device [37][lx][ly]);
- * shifted storage keeps g = f - w_p rounded to nearest even. */
+/* Replace the current populations from canonical FP64 (device [37][lx][ly],
+ * read only; same order as lb_get_populations), converted to the storage
+ * layout of Fig. 2 (Section 4). Shifted storage keeps g = f - w_p rounded
+ * to nearest even. Invalidates a fused audit. LB_EINVAL for a NULL context
+ * or array. Asynchronous. */
 int lb_set_populations(lb_ctx *ctx, const double *f);
 
 /* Lattice totals in FP64 on the host: out = {mass, x-momentum, y-momentum,
- * energy = 1/2 sum f |xi|^2}, summed in a fixed order (run to run
+ * energy = 1/2 sum f |xi|^2}, the quantities the collide conserves (paper,
+ * Section 3: collide keeps density, momentum and energy of every site;
+ * propagate only moves populations), summed in a fixed order (run to run
  * reproducible). Uses the sums fused into the last lb_step when they are
  * still current, else reduces the current buffer. Synchronises the stream.
- * Returns LB_ENONFINITE (with out filled) if any total is NaN or Inf. */
+ * Returns LB_ENONFINITE (with out filled) if any total is NaN or Inf,
+ * LB_EINVAL for a NULL context or out, LB_EDEVICE on a HIP error (including
+ * a fault of earlier asynchronous work). */
 int lb_audit(lb_ctx *ctx, double out[4]);
 
 /* Index (0 or 1) of the buffer holding the current state. */

@@ -72,6 +72,16 @@ int64_t div_up(int64_t a, int64_t b) { return (a + b - 1) / b; }
 
 size_t round256(size_t b) { return (b + 255) & ~(size_t)255; }
 
+// The kernels keep each lane's in-row column term as a 32-bit byte offset
+// (Stencil::col): the bytes of one lattice row within one population term
+// must not exceed 4 GiB. That is LY * 37 elements for AoS and CAoSoA (all
+// populations of a row interleaved) and LY elements for SoA and CSoA.
+bool row_bytes_ok(int32_t ly, int eb, int layout)
+{
+    const uint64_t per = (layout == LB_AOS || layout == LB_CAOSOA) ? (uint64_t)Q * eb : (uint64_t)eb;
+    return (uint64_t)ly * per <= ((uint64_t)1 << 32);
+}
+
 // Calls f(P{}, L{}) for the runtime precision and layout.
 template <class P, class F>
 void with_layout(int layout, F&& f)
@@ -115,6 +125,7 @@ size_t lb_buffer_bytes(int32_t lx, int32_t ly, int32_t precision, int32_t layout
     if (lx < 1 || ly < 1 || eb == 0 || !layout_ok(layout)) return 0;
     const int64_t n = (int64_t)lx * ly;
     if (n >= ((int64_t)1 << 31)) return 0;
+    if (!row_bytes_ok(ly, eb, layout)) return 0;
     if (layout == LB_CSOA || layout == LB_CAOSOA) {
         const int vl = 128 / eb;
         if (ly % vl != 0) return 0;
@@ -146,6 +157,10 @@ int lb_init(lb_ctx** out, const lb_config* cfg, const double* rho, const double*
         return fail(nullptr, LB_EINVAL, "lb_init: tau = %g must be finite and > 0.5", k.tau);
     if (elem_bytes(k.precision) == 0) return fail(nullptr, LB_EUNSUPPORTED, "lb_init: unknown precision %d", k.precision);
     if (!layout_ok(k.layout)) return fail(nullptr, LB_EUNSUPPORTED, "lb_init: unknown layout %d", k.layout);
+    if (!row_bytes_ok(k.ly, elem_bytes(k.precision), k.layout))
+        return fail(nullptr, LB_EUNSUPPORTED,
+                    "lb_init: a row of %d sites spans more than 4 GiB per population term in layout %d", k.ly,
+                    k.layout);
     const size_t bb = lb_buffer_bytes(k.lx, k.ly, k.precision, k.layout);
     if (bb == 0)
         return fail(nullptr, LB_EUNSUPPORTED, "lb_init: layout %d needs LY (%d) to be a multiple of %d", k.layout,

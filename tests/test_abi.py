@@ -67,6 +67,37 @@ def test_buffer_and_scratch_sizes():
     assert lb.scratch_bytes(1, 1) >= 5 * 8
 
 
+# Rows longer than the kernels' 32-bit in-row byte offsets can address:
+# ly * 37 * elem > 2^32 (AoS, CAoSoA) or ly * elem > 2^32 (SoA, CSoA).
+ROW_LIMIT = [
+    (8, 2 ** 24, "f64", "caosoa"),     # 8 x 2^24 FP64: two 39.7 GB buffers would fit the GPU
+    (8, 2 ** 24, "f64", "aos"),
+    (1, 60_000_000, "f16s", "aos"),    # 4.4 GB per buffer
+    (1, 60_000_000, "f16s", "caosoa"),
+    (3, 600_000_000, "f64", "soa"),    # 4.8e9 bytes in one population row
+    (3, 600_000_000, "f64", "csoa"),
+]
+
+
+@pytest.mark.parametrize("lx,ly,prec,layout", ROW_LIMIT)
+def test_buffer_bytes_rejects_rows_beyond_32bit_offsets(lx, ly, prec, layout):
+    assert lb.buffer_bytes(lx, ly, prec, layout) == 0
+
+
+def test_row_limit_boundary():
+    # the largest accepted rows: ly * 37 * 8 <= 2^32 and ly * 8 <= 2^32
+    last = (2 ** 32) // (37 * 8)
+    assert lb.buffer_bytes(1, last, "f64", "aos") > 0
+    assert lb.buffer_bytes(1, last + 1, "f64", "aos") == 0
+    last_c = last - last % 16
+    assert lb.buffer_bytes(1, last_c, "f64", "caosoa") > 0
+    assert lb.buffer_bytes(1, last_c + 16, "f64", "caosoa") == 0
+    assert lb.buffer_bytes(1, 2 ** 29, "f64", "soa") > 0
+    assert lb.buffer_bytes(1, 2 ** 29 + 1, "f64", "soa") == 0
+    # the same rows in SoA fit: only the interleaved layouts hit the limit
+    assert lb.buffer_bytes(8, 2 ** 24, "f64", "soa") == 8 * 2 ** 24 * 37 * 8
+
+
 def _cfg(**kw):
     c = lb.Config()
     c.lx, c.ly, c.tau = kw.get("lx", 8), kw.get("ly", 16), kw.get("tau", 0.8)
@@ -104,6 +135,19 @@ def test_init_rejects_before_device_work(kw, code):
     assert rc == code
     assert not ctx.value
     assert lb.lib().lb_last_error(None).decode()
+
+
+@pytest.mark.parametrize("lx,ly,prec,layout", ROW_LIMIT)
+def test_init_rejects_rows_beyond_32bit_offsets(lx, ly, prec, layout):
+    """Refused by validation with LB_EUNSUPPORTED; the fake device
+    addresses are never touched (no kernel is launched)."""
+    ctx = ctypes.c_void_p()
+    cfg = _cfg(lx=lx, ly=ly, precision=lb.PRECISIONS[prec], layout=lb.LAYOUTS[layout], scratch_bytes=1 << 40)
+    fake = 0x40000
+    rc = lb.lib().lb_init(ctypes.byref(ctx), ctypes.byref(cfg), fake, fake, fake, fake)
+    assert rc == lb.LB_EUNSUPPORTED
+    assert not ctx.value
+    assert b"4 GiB" in lb.lib().lb_last_error(None)
 
 
 def test_init_null_arguments():
