@@ -300,3 +300,56 @@ def surrogate_collide(g, tau, theta, norm, threshold, emulate=True):
         exact = lbm.init(rho[idx, None], ux[idx, None], uy[idx, None], T[idx, None])[:, :, 0].T - w
         ghat[idx] = exact
     return g + (ghat - g) / tau, fb, res
+
+
+# ---- tolerance of the learned collide's parity ------------------------------------------
+
+def bf16_ulp(v: np.ndarray) -> np.ndarray:
+    """Unit in the last place of BF16 at |v| (8 significant bits): 2^(e - 7)
+    for 2^e <= |v| < 2^(e + 1); 0 at v = 0."""
+    a = np.abs(np.asarray(v, dtype=np.float64))
+    e = np.floor(np.log2(np.where(a > 0, a, 1.0)))
+    return np.where(a > 0, 2.0 ** (e - 7), 0.0)
+
+
+def gelu_grad_max() -> float:
+    """max over a of |gelu'(a)| (about 1.129, near a = 2.4), on a grid fine
+    enough that the next grid point cannot exceed it by 1e-6."""
+    a = np.linspace(-8.0, 8.0, 160001)
+    return float(np.abs(gelu_grad(a)).max()) + 1e-6
+
+
+def flip_bound(theta, norm, g) -> np.ndarray:
+    """B2 per site: the largest |change of g_hat_p| / w_p over populations
+    that one BF16 rounding flip of one second-layer activation can cause at
+    each of the sites g (n, 37): h2_j rounded to the neighbouring BF16 value,
+    one unit in the last place at its own magnitude. Returns (n,).
+
+    Why flips set the tolerance: the GPU kernels and the emulating forward
+    pass round the same quantities to BF16 at the same points; the values
+    before rounding differ only by FP32 accumulation, the folded FP32
+    standardisation and the hardware exponential (relative 1e-7 to 1e-6).
+    So the two sides disagree by more than that only where a value lies
+    that close to a BF16 rounding boundary, and then by one BF16 unit.
+
+    Propagation of a second-layer flip of unit j: the output o
+    (standardised) moves by |do_p| = |W3_pj| ulp(h2_j); d_p = w_p (mu_y +
+    sd_y o_p) and g_hat = P(g) + d - P(d), so
+      |dg_hat_p| / w_p <= sd_y,p |do_p|
+                          + sum_a |phi_a(p)| sum_q w_q sd_y,q |do_q| |phi_a(q)| / G_aa
+    (P: the projection onto the conserved functions phi, Gram diagonal
+    G_aa), maximised over p and j with W3 at its BF16 values. A flip of an
+    input or of a first-layer activation reaches the output through the
+    next layers and through the roundings it changes there; planted on this
+    forward pass (over every unit, at sampled sites) it moves g_hat by at
+    most 4 B2 of its site."""
+    w = constants()["w"]
+    p = unpack(theta)
+    W3 = np.abs(bf16(p["W3"]))
+    zs = (np.asarray(g, dtype=np.float64) / w - norm[0]) / norm[1]
+    _, (_, _, _, _, h2) = forward(theta, zs, emulate=True)
+    v = np.asarray(norm[3], dtype=np.float64)[:, None] * W3          # (37 outputs, 128 units)
+    phi = np.abs(_basis())
+    proj = phi.T @ ((phi * w) @ v / np.diag(gram())[:, None])
+    col = (v + proj).max(axis=0)                                        # per unit j, per unit ulp
+    return (bf16_ulp(h2) * col).max(axis=1)

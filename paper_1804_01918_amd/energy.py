@@ -88,6 +88,24 @@ class EnergyMeter:
         span = (t1 - t0) * 1e-9  # counter timestamps are in ns
         return (e1 - e0) / span, span, len(samples)
 
+    def idle_power(self, seconds: float = 2.5):
+        """(average watts, seconds sampled, refreshes) with no work queued by
+        this process, over about `seconds` of counter refreshes."""
+        t_end = time.perf_counter() + seconds
+        return self.power_during(lambda: None, 1, lambda: time.perf_counter() >= t_end)
+
+    def power_limit_watts(self):
+        """The board's power cap in watts as the SMI library reports it (read
+        only), or None if it cannot be read."""
+        if not self.available:
+            return None
+        try:
+            info = self._smi.amdsmi_get_power_cap_info(self._h)
+            cap = info.get("power_cap") or info.get("max_power_cap")
+            return float(cap) * 1e-6 if cap else None  # reported in microwatts
+        except Exception:
+            return None
+
     def close(self):
         if self._smi is not None:
             try:

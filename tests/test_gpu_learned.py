@@ -12,9 +12,22 @@ Tolerances:
   the kernels and the BF16-emulating oracle round at the same points, so the
   residue is FP32 versus FP64 accumulation plus rare BF16 ties that round the
   other way;
-* learned equilibrium: |g_hat_gpu - g_hat_oracle| / w_p <= 2e-3 (the same
-  BF16 ties, each worth 2^-8 of an activation), and the conserved moments of
-  g_hat equal those of the input to FP32 rounding.
+* learned equilibrium g_hat, per site, in units of w_p (a step relaxes by
+  1/tau, so the step bars are these divided by tau):
+  - every site: <= 8 B2, B2 = surrogate.flip_bound of that site, the move
+    of g_hat that one BF16 rounding flip of a second-layer activation
+    causes there. Both sides round the same values to BF16 and differ
+    before rounding only by FP32 accumulation, the folded standardisation
+    and the hardware exponential, so they disagree only where a value sits
+    that close to a rounding boundary, and then by one BF16 unit; one flip
+    anywhere in the network (input, first or second layer, with the
+    roundings it changes downstream) moves g_hat by at most 4 B2 (pinned on
+    the oracle by planting flips), and 8 B2 allows two at one site;
+  - the median site: <= 1e-6 (FLOOR): at a site without a flip only the
+    FP32 arithmetic differs (measured about 2e-8), so an error common to
+    all sites (a permuted weight column, a dropped bias, a wrong
+    standardisation constant) fails here even where it stays under 5 B2;
+  - conserved moments of g_hat equal those of the input to FP32 rounding.
 """
 import numpy as np
 import pytest
@@ -29,6 +42,29 @@ torch = pytest.importorskip("torch")
 from paper_1804_01918_amd import lb  # noqa: E402
 
 TAU = 0.8
+FLOOR = 1e-6  # per-site agreement without a BF16 flip (FP32 arithmetic only)
+
+
+def _bar(theta, nf, g):
+    """Largest |g_hat_gpu - g_hat_oracle| / w_p allowed at each of the sites
+    g: two BF16 flips of 4 B2 each (see the module docstring)."""
+    return 8.0 * S.flip_bound(theta, nf, g)
+
+
+def _check_sites(err, bar, floor=FLOOR, what=""):
+    """err: per-site max over populations; bar: per-site bars (or one).
+    Every site within its bar, the median site within floor. Prints the
+    distribution."""
+    err = np.asarray(err, dtype=np.float64)
+    bar = np.broadcast_to(np.asarray(bar, dtype=np.float64), err.shape)
+    frac = float(np.mean(err > floor))
+    worst = int(np.argmax(err / bar))
+    print(f"{what} sites={err.size} max={err.max():.3e} worst/bar={err[worst] / bar[worst]:.3f} "
+          f"bar range=[{bar.min():.2e}, {bar.max():.2e}] median={np.median(err):.3e} floor={floor:.1e} "
+          f"above_floor={frac:.4f}")
+    assert np.all(err <= bar), (err[worst], bar[worst])
+    assert np.median(err) <= floor, (np.median(err), floor)
+    return frac
 
 
 def _f32(a):
@@ -174,7 +210,7 @@ def test_learned_equilibrium_matches_oracle(consts, oracle_net):
     assert np.array_equal(fb.cpu().numpy().astype(bool), ~box)
     exact = lbm.init(rho[:, None], ux[:, None], uy[:, None], T[:, None])[:, :, 0].T - w
     want = np.where(box[:, None], want, exact)
-    assert np.max(np.abs(gh - want) / w) <= 2e-3
+    _check_sites(np.max(np.abs(gh - want) / w, axis=1), _bar(theta, nf, pre), what="equilibrium")
     # projection: conserved moments of g_hat are those of the input
     for phi in S._basis():
         scale = np.abs(pre * phi).sum(1) + 1e-3
@@ -223,7 +259,9 @@ def test_learned_step_matches_oracle(consts, oracle_net, kind):
         return (out + w).T.reshape(win.shape)
 
     ref = np.stack([_window_step(fields, s, collide) for s in sites])
-    assert np.max(np.abs(got - ref) / w) <= 2e-3 / TAU
+    pulled = np.stack([_window_step(fields, s, lambda win: win) for s in sites]) - w
+    _check_sites(np.max(np.abs(got - ref) / w, axis=1), _bar(theta, nf, pulled) / TAU, FLOOR / TAU,
+                 what=f"step {kind}")
 
 
 def _learned_sampled_parity(consts, oracle_net, lx, ly, layout, kind, sites, seed=2):
@@ -249,7 +287,8 @@ def _learned_sampled_parity(consts, oracle_net, lx, ly, layout, kind, sites, see
         return (out + w).T.reshape(win.shape)
 
     ref = np.stack([_window_step(fields, s, collide) for s in sites])
-    return np.max(np.abs(got - ref) / w)
+    pulled = np.stack([_window_step(fields, s, lambda win: win) for s in sites]) - w
+    return np.max(np.abs(got - ref) / w, axis=1), _bar(theta, nf, pulled) / TAU
 
 
 @pytest.mark.parametrize("L,kind", [(2048, "shear_wave"), (8192, "rayleigh_taylor")])
@@ -261,7 +300,8 @@ def test_learned_step_full_size_sampled(consts, oracle_net, L, kind):
     rng = np.random.default_rng(5)
     sites = [(0, 0), (lx - 1, ly - 1), (0, ly - 1), (lx - 1, 0), (L // 2, 511), (L // 2, 512), (7, L - 513),
              (L - 48, L // 2)] + [(int(x), int(y)) for x, y in rng.integers(0, L, size=(8, 2))]
-    assert _learned_sampled_parity(consts, oracle_net, lx, ly, "caosoa", kind, sites) <= 2e-3 / TAU
+    err, bar = _learned_sampled_parity(consts, oracle_net, lx, ly, "caosoa", kind, sites)
+    _check_sites(err, bar, FLOOR / TAU, what=f"full size {L}")
 
 
 @pytest.mark.parametrize("lx,ly,layout", [(1, 1, "soa"), (1, 5, "aos"), (3, 96, "aos"), (3, 96, "csoa"),
@@ -274,7 +314,8 @@ def test_learned_step_ragged_tiles(consts, oracle_net, lx, ly, layout):
     if ly > 512:
         sites += [(2, 511), (2, 512), (lx - 2, 600)]
     sites = sorted({(x % lx, y % ly) for x, y in sites})
-    assert _learned_sampled_parity(consts, oracle_net, lx, ly, layout, "rayleigh_taylor", sites) <= 2e-3 / TAU
+    err, bar = _learned_sampled_parity(consts, oracle_net, lx, ly, layout, "rayleigh_taylor", sites)
+    _check_sites(err, bar, FLOOR / TAU, what=f"ragged {lx}x{ly} {layout}")
 
 
 def _window_step(fields, site, collide):
@@ -438,3 +479,107 @@ def test_trained_network_gain(consts):
     assert out["untrained"][0] >= 0.9
     trained.close()
     untrained.close()
+
+
+@pytest.fixture(scope="module")
+def mixed_state(consts, oracle_net):
+    """A 256 x 1536 Rayleigh-Taylor-like lattice in which a random tenth of
+    the sites (scattered, not whole rows or tiles) start at T = 1.6, outside
+    the training box (after the pull a site mixes populations from 37
+    neighbours, so these sites and some of their neighbours fall back). 768 row tiles of 512 sites: three per persistent
+    workgroup on 256 compute units, so a wavefront's fallback queue carries
+    partial batches from tile to tile, and rows of three tiles.
+
+    The oracle side: the FP32-shifted initial state, one pull propagate,
+    then for every site both branches of the learned collide (network
+    equilibrium; plain equilibrium) with the residual and the box verdict."""
+    theta, norm, _ = oracle_net
+    w = consts["w"]
+    lx, ly = 256, 1536
+    rho, ux, uy, T = inputs.rayleigh_taylor(lx, ly, seed=6)
+    hot = np.random.default_rng(11).random((lx, ly)) < 0.1
+    T = np.where(hot, 1.6, T)
+    fields = (rho, ux, uy, T)
+    f0 = lbm.init(*fields)
+    f0 = w[:, None, None] + _f32(f0 - w[:, None, None])
+    g = (lbm.propagate(f0) - w[:, None, None]).reshape(37, -1).T.copy()   # (sites, 37), x-major
+    m = _gpu_net(theta, norm)
+    nf = m.get_normalization().astype(np.float64)
+    m.close()
+    n = g.shape[0]
+    learned = np.empty_like(g)
+    plain = np.empty_like(g)
+    res = np.empty(n)
+    box = np.empty(n, dtype=bool)
+    edge = np.empty(n, dtype=bool)  # within FP32 reach of a training-box edge: either verdict
+    bar = np.empty(n)
+    for a in range(0, n, 32768):
+        b = min(n, a + 32768)
+        ga = g[a:b]
+        rho_, ux_, uy_, T_ = S.macro(ga)
+        gh = S.surrogate_equilibrium(ga, theta, nf, emulate=True)
+        res[a:b] = S.residual(gh, rho_, ux_, uy_, T_)
+        box[a:b] = S.in_box(rho_, ux_, uy_, T_)
+        speed = np.sqrt(ux_ * ux_ + uy_ * uy_)
+        edge[a:b] = ((np.minimum(np.abs(rho_ - 0.9), np.abs(rho_ - 1.1)) < 1e-5)
+                     | (np.minimum(np.abs(T_ - 0.9), np.abs(T_ - 1.1)) < 1e-5) | (np.abs(speed - 0.1) < 1e-5))
+        exact = lbm.init(rho_[:, None], ux_[:, None], uy_[:, None], T_[:, None])[:, :, 0].T - w
+        learned[a:b] = ga + (gh - ga) / TAU
+        plain[a:b] = ga + (exact - ga) / TAU
+        bar[a:b] = _bar(theta, nf, ga) / TAU
+    return dict(fields=fields, lx=lx, ly=ly, g=g, learned=learned, plain=plain, res=res, box=box, edge=edge,
+                nf=nf, bar=bar)
+
+
+@pytest.mark.parametrize("thr_kind", ["box_only", "median_residual"])
+@pytest.mark.parametrize("path", ["fused", "in_place"])
+def test_learned_mixed_verdicts_every_site(consts, oracle_net, mixed_state, thr_kind, path):
+    """Every site of a lattice with scattered fallback sites against the
+    oracle's learned collide: the fused step into a destination filled with
+    0xFF bytes (NaN, so a site never written shows), and propagate followed
+    by the in-place collide. Verdicts: with threshold 1e9 only the training
+    box decides (clear-cut here); with the median residual as threshold the
+    residual decides too, and sites whose oracle residual lies within 5 % of
+    the threshold may take either branch (the GPU's residual comes from its
+    own FP32 network pass), but must then equal that branch. Fallback sites
+    take the plain FP32 collide: within 2e-6 of the FP64 plain collide per
+    w_p (FP32 rounding of deviations up to about 1.5 w_p). The fallback
+    count equals the number of fallback verdicts."""
+    theta, norm, _ = oracle_net
+    st = mixed_state
+    w = consts["w"]
+    lx, ly = st["lx"], st["ly"]
+    res, box = st["res"], st["box"]
+    if thr_kind == "box_only":
+        thr = 1e9
+        tie = st["edge"].copy()
+    else:
+        thr = float(np.median(res[box]))
+        tie = st["edge"] | (box & (np.abs(res - thr) <= 0.05 * thr))
+    fb = ~box | (res > thr)
+    m = _gpu_net(theta, norm)
+    with lb.Lattice(lx, ly, TAU, [torch.from_numpy(a).cuda() for a in st["fields"]], precision="f32s",
+                    layout="caosoa") as lat:
+        lat.set_surrogate(m, thr)
+        if path == "fused":
+            lat.bufs[1 - lat.current_buffer()].fill_(0xFF)
+            lat.step(1)
+        else:
+            lat.propagate()
+            lat.collide()
+        got = (lat.get_populations().cpu().numpy() - w[:, None, None]).reshape(37, -1).T
+        nfb, ntot = lat.surrogate_counts()
+    m.close()
+    assert np.isfinite(got).all()
+    err_l = np.max(np.abs(got - st["learned"]) / w, axis=1)
+    err_p = np.max(np.abs(got - st["plain"]) / w, axis=1)
+    print(f"{path} {thr_kind}: fallback {int(fb.sum())} of {fb.size}, ties {int(tie.sum())}, gpu count {nfb}")
+    assert ntot == lx * ly
+    clear_l = ~fb & ~tie
+    clear_p = fb & ~tie
+    _check_sites(err_l[clear_l], st["bar"][clear_l], FLOOR / TAU, what=f"{path} {thr_kind} learned sites")
+    assert err_p[clear_p].max() <= 2e-6, err_p[clear_p].max()
+    took_plain = err_p <= 2e-6
+    assert np.all((err_l[tie] <= st["bar"][tie]) | took_plain[tie])
+    assert nfb == int(clear_p.sum()) + int(took_plain[tie].sum())
+    assert 0.05 * fb.size < fb.sum() < 0.95 * fb.size  # both branches well represented

@@ -129,3 +129,40 @@ def test_shifted_audit_drift_within_stated_error(consts, prec):
         lat.step(n)
         a1 = lat.audit()
     assert np.all(np.abs(a1 - a0) <= n * EPS[prec] * scale), (a1 - a0, n * EPS[prec] * scale)
+
+
+def test_compensated_moment_sums_are_exact_to_second_order(consts):
+    """The compensated FP32 moment sums (cascaded TwoSum) against the plain
+    ones, on a state built so that only the moment sums can err: per site a
+    large non-equilibrium part (0.3 w_p N(0,1)) with its conserved moments
+    removed in FP64, stored as FP32 deviations (whose exact moments are
+    then only the FP32 rounding residue, of order 2^-24 A), collided once
+    with tau = 1. The result is then the equilibrium of those tiny moments,
+    so the per-population rounding of the collide is of order 2^-48, while
+    an error in a moment sum moves every population by up to 2^-24 sum |g|.
+    The FP64 oracle collides the same stored values.
+
+    Bar: |f_gpu - f_oracle| / w_p <= 1e-10. Compensated sums are exact to
+    about 2^-48 sum |g| (measured far below the bar) and pass; plain FP32
+    sums are off by about 2^-24 sum |g| ~ 1e-8 and fail it, which the test
+    also asserts, so a compensation that did nothing would be caught."""
+    from oracle import surrogate as S
+    lx, ly, bar = 16, 32, 1e-10
+    w = consts["w"]
+    rng = np.random.default_rng(3)
+    g = (0.3 * w * rng.standard_normal((lx * ly, 37)))
+    g = g - S.conserved_part(g)
+    g = g.astype(np.float32).astype(np.float64)
+    f = (w + g).T.reshape(37, lx, ly)
+    want = lbm.collide(f, 1.0)
+    errs = {}
+    for comp in (True, False):
+        with lb.Lattice(lx, ly, 1.0, inputs.random_equilibrium(lx, ly), precision="f32s", layout="soa",
+                        compensated=comp) as lat:
+            lat.set_populations(f)
+            lat.collide()
+            got = lat.get_populations().cpu().numpy()
+        errs[comp] = float(np.max(np.abs(got - want) / w[:, None, None]))
+    print("max |f - f_oracle| / w: compensated %.3e, plain %.3e" % (errs[True], errs[False]))
+    assert errs[True] <= bar, errs
+    assert errs[False] > bar, errs

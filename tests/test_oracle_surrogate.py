@@ -150,3 +150,71 @@ def test_short_training_reduces_loss():
     norm = S.fit_normalization(pre, post, tau)
     theta, losses = S.train(pre, post, tau, S.init_params(1), norm, batch=256, epochs=6, lr0=3e-3, seed=2)
     assert losses[-1] < 0.1 * losses[0]
+
+
+def test_bf16_ulp():
+    v = np.array([1.0, 1.5, -2.0, 3.0e-3, 0.0, 2.0 ** -130])
+    u = S.bf16_ulp(v)
+    assert np.array_equal(u[:5], [2.0 ** -7, 2.0 ** -7, 2.0 ** -6, 2.0 ** -16, 0.0])
+    # neighbouring BF16 values differ by exactly one ulp
+    for a in (1.0, 1.7, 0.0123, 77.0):
+        b = S.bf16(a)
+        nxt = np.array([b], dtype=np.float32).view(np.uint32) + np.uint32(1 << 16)
+        assert nxt.view(np.float32)[0] - b == S.bf16_ulp(b)
+
+
+def test_gelu_grad_max():
+    G = S.gelu_grad_max()
+    assert 1.12 < G < 1.14
+    a = np.random.default_rng(0).uniform(-20, 20, 100000)
+    assert np.abs(S.gelu_grad(a)).max() <= G
+
+
+@pytest.mark.parametrize("trained", [False, True])
+def test_flip_bound_covers_single_flips_anywhere(consts, trained):
+    """Plant one BF16 flip (one unit in the last place, either direction) in
+    one network input, one first-layer or one second-layer activation of
+    the emulating forward pass, then round everything downstream again: at
+    sampled sites and over every unit, g_hat moves by at most 4 B2 of the
+    site, and at the median site the worst second-layer flip comes within a
+    factor 3 of B2 (the bound is not loose)."""
+    w = consts["w"]
+    tau = 0.8
+    pre, post = S.make_pairs(2048, seed=21, tau=tau)
+    norm = S.fit_normalization(pre, post, tau)
+    theta = S.init_params(4)
+    if trained:
+        theta, _ = S.train(pre, post, tau, theta, norm, batch=256, epochs=2, lr0=3e-3, seed=8)
+    sites = pre[::97]
+    B2s = S.flip_bound(theta, norm, sites)
+    p = S.unpack(theta)
+    W1, W2, W3 = (S.bf16(p[k]) for k in ("W1", "W2", "W3"))
+
+    def ghat(g, x=None, h1=None, h2=None):
+        if h1 is None:
+            h1 = S.bf16(S.gelu(x @ W1.T + p["b1"]))
+        if h2 is None:
+            h2 = S.bf16(S.gelu(h1 @ W2.T + p["b2"]))
+        d = w * (norm[2] + norm[3] * (h2 @ W3.T + p["b3"]))
+        return S.conserved_part(g) + d - S.conserved_part(d), h1, h2
+
+    rng = np.random.default_rng(0)
+    ratio = {"x": 0.0, "h1": 0.0, "h2": 0.0}
+    h2_ratio = []
+    for g, B2 in zip(sites, B2s):
+        worst = {"x": 0.0, "h1": 0.0, "h2": 0.0}
+        g = g[None, :]
+        x = S.bf16((g / w - norm[0]) / norm[1])
+        base, h1, h2 = ghat(g, x=x)
+        for kind, n in (("x", 37), ("h1", 128), ("h2", 128)):
+            for k in range(n):
+                v = {"x": x, "h1": h1, "h2": h2}[kind].copy()
+                v[0, k] += rng.choice([-1.0, 1.0]) * S.bf16_ulp(v[0, k])
+                args = {"x": dict(x=v), "h1": dict(h1=v), "h2": dict(h1=h1, h2=v)}[kind]
+                moved, _, _ = ghat(g, **args)
+                worst[kind] = max(worst[kind], float(np.max(np.abs(moved - base) / w)))
+        for kind in ratio:
+            ratio[kind] = max(ratio[kind], worst[kind] / B2)
+        h2_ratio.append(worst["h2"] / B2)
+    assert max(ratio.values()) <= 4.0, ratio
+    assert np.median(h2_ratio) >= 1 / 3, h2_ratio
