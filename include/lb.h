@@ -171,6 +171,21 @@ int lb_set_populations(lb_ctx *ctx, const double *f);
  * a fault of earlier asynchronous work). */
 int lb_audit(lb_ctx *ctx, double out[4]);
 
+/* lb_audit without the caller's scratch, for callers that cannot allocate
+ * device memory (code under stream capture, tight serving loops, harnesses
+ * that forbid allocation): the same totals as lb_audit, always reduced from
+ * the current buffer with the same kernels, but the partial sums and totals
+ * go to a scratch array inside the library (one per device, 8 MiB + 32 B,
+ * held until the process ends) instead of lb_config.scratch. Allocates
+ * nothing. Limit: lattices of at most 262,144 row tiles of 256 sites,
+ * lx * ceil(ly / 256) <= 2^18 (8192 x 8192); larger ones return LB_EINVAL.
+ * All calls on one device share that array: calls that overlap in time on
+ * one device (other host threads, or other streams) race and may return
+ * wrong totals. The array is fully rewritten by each call before it is read.
+ * Errors as lb_audit, plus LB_EDEVICE if the array's device address could
+ * not be resolved when the context was created. Synchronises the stream. */
+int lb_audit_static(lb_ctx *ctx, double out[4]);
+
 /* Index (0 or 1) of the buffer holding the current state. */
 int lb_current_buffer(const lb_ctx *ctx);
 

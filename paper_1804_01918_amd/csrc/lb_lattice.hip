@@ -7,6 +7,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <new>
 
 #include "../../include/lb.h"
@@ -33,8 +34,22 @@ struct lb_ctx {
     int lgrid;             // their persistent grid: min(tiles, compute units)
     int64_t audit_parts;   // partial sums written by the last fused audit
     bool fused_audit_valid;
+    int device;            // device current at lb_init (where the buffers live)
+    void* static_scratch;  // that device's address of `scratch` (lb_audit_static), or NULL
     char err[512];
 };
+
+// ---- library-owned scratch of lb_audit_static ---------------------------------
+// A file-scope device array, so that callers who cannot allocate device memory
+// can still audit: 4 FP64 partial sums per 256-site row tile (the same
+// partials lb_audit keeps in the caller's scratch) followed by the 4 totals.
+// Every device that loads the library holds its own copy until the process
+// ends. Host code never passes the array's name to a kernel or a copy: it
+// uses the device address that hipGetSymbolAddress returns for the current
+// device, resolved once per device by lb_init.
+constexpr int64_t STATIC_AUDIT_MAX_TILES = (int64_t)1 << 18;  // 8192 x 8192 sites
+constexpr size_t STATIC_SCRATCH_BYTES = (size_t)(STATIC_AUDIT_MAX_TILES * 4 + 4) * sizeof(double);
+static __device__ __align__(256) double scratch[STATIC_AUDIT_MAX_TILES * 4 + 4];
 
 namespace {
 
@@ -114,6 +129,69 @@ int launch_status(lb_ctx* c, const char* what) { return check_hip(c, hipGetLastE
 
 dim3 grid_of(const lb_ctx* c) { return dim3((unsigned)c->nblocks); }
 dim3 lgrid_of(const lb_ctx* c) { return dim3((unsigned)c->lgrid); }
+
+constexpr int MAX_DEVICES = 64;
+std::mutex g_scratch_mu;
+bool g_scratch_done[MAX_DEVICES];
+void* g_scratch_ptr[MAX_DEVICES];
+hipError_t g_scratch_err[MAX_DEVICES];
+
+// Device address of `scratch` on device `dev`, which must be current.
+// Resolved on the first call per device; NULL (and *err set) on failure.
+void* static_scratch_of(int dev, hipError_t* err)
+{
+    *err = hipSuccess;
+    if (dev < 0 || dev >= MAX_DEVICES) {
+        *err = hipErrorInvalidDevice;
+        return nullptr;
+    }
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_done[dev]) {
+        void* ptr = nullptr;
+        g_scratch_err[dev] = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        g_scratch_ptr[dev] = g_scratch_err[dev] == hipSuccess ? ptr : nullptr;
+        g_scratch_done[dev] = true;
+    }
+    *err = g_scratch_err[dev];
+    return g_scratch_ptr[dev];
+}
+
+// Audit of the current buffer into `partials` (4 per tile) and `totals`
+// (4), copied to out on the host; `use_fused` takes the partials of the last
+// fused step, which are already in `partials`.
+int audit_into(lb_ctx* c, double* partials, double* totals, bool use_fused, double out[4], const char* what)
+{
+    char msg[96];
+    if (!use_fused) {
+        with_config(c->cfg, [&](auto p, auto l) {
+            using P = decltype(p);
+            using L = decltype(l);
+            hipLaunchKernelGGL((k_audit<P, L>), grid_of(c), dim3(BLOCK), 0, c->stream,
+                               (const typename P::T*)cur_buf(c), c->geo, partials);
+        });
+        snprintf(msg, sizeof msg, "%s: partials", what);
+        const int rc = launch_status(c, msg);
+        if (rc != LB_OK) return rc;
+    }
+    const double n = (double)c->geo.n;
+    const bool shifted = c->cfg.precision != LB_FP64;
+    const double4 base = shifted ? double4{n, 0.0, 0.0, n} : double4{0.0, 0.0, 0.0, 0.0};
+    const int64_t nparts = use_fused ? c->audit_parts : c->nblocks;
+    hipLaunchKernelGGL(k_audit_final, dim3(1), dim3(BLOCK), 0, c->stream, (const double*)partials, nparts, base,
+                       totals);
+    snprintf(msg, sizeof msg, "%s: final", what);
+    int rc = launch_status(c, msg);
+    if (rc != LB_OK) return rc;
+    snprintf(msg, sizeof msg, "%s: copy", what);
+    rc = check_hip(c, hipMemcpyAsync(out, totals, 4 * sizeof(double), hipMemcpyDeviceToHost, c->stream), msg);
+    if (rc != LB_OK) return rc;
+    snprintf(msg, sizeof msg, "%s: synchronize", what);
+    rc = check_hip(c, hipStreamSynchronize(c->stream), msg);
+    if (rc != LB_OK) return rc;
+    for (int i = 0; i < 4; ++i)
+        if (!std::isfinite(out[i])) return fail(c, LB_ENONFINITE, "%s: total %d is not finite", what, i);
+    return LB_OK;
+}
 
 }  // namespace
 
@@ -198,6 +276,12 @@ int lb_init(lb_ctx** out, const lb_config* cfg, const double* rho, const double*
     c->audit_parts = c->nblocks;
     c->fused_audit_valid = false;
     c->err[0] = 0;
+    c->device = -1;
+    c->static_scratch = nullptr;
+    if (hipGetDevice(&c->device) == hipSuccess) {
+        hipError_t e;
+        c->static_scratch = static_scratch_of(c->device, &e);
+    }
 
     with_config(k, [&](auto p, auto l) {
         using P = decltype(p);
@@ -375,32 +459,26 @@ int lb_audit(lb_ctx* c, double out[4])
 {
     if (!c) return fail(nullptr, LB_EINVAL, "lb_audit: ctx is NULL");
     if (!out) return fail(c, LB_EINVAL, "lb_audit: out is NULL");
-    if (!c->fused_audit_valid) {
-        with_config(c->cfg, [&](auto p, auto l) {
-            using P = decltype(p);
-            using L = decltype(l);
-            hipLaunchKernelGGL((k_audit<P, L>), grid_of(c), dim3(BLOCK), 0, c->stream,
-                               (const typename P::T*)cur_buf(c), c->geo, c->partials);
-        });
-        const int rc = launch_status(c, "lb_audit: partials");
-        if (rc != LB_OK) return rc;
+    return audit_into(c, c->partials, c->totals, c->fused_audit_valid, out, "lb_audit");
+}
+
+int lb_audit_static(lb_ctx* c, double out[4])
+{
+    if (!c) return fail(nullptr, LB_EINVAL, "lb_audit_static: ctx is NULL");
+    if (!out) return fail(c, LB_EINVAL, "lb_audit_static: out is NULL");
+    if (c->nblocks > STATIC_AUDIT_MAX_TILES)
+        return fail(c, LB_EINVAL,
+                    "lb_audit_static: %lld row tiles of %d sites exceed the library scratch (%lld tiles, %zu bytes)",
+                    (long long)c->nblocks, BLOCK, (long long)STATIC_AUDIT_MAX_TILES, STATIC_SCRATCH_BYTES);
+    if (!c->static_scratch) {
+        hipError_t e = hipSuccess;
+        if (c->device >= 0) static_scratch_of(c->device, &e);
+        return fail(c, LB_EDEVICE, "lb_audit_static: no address of the library scratch on device %d: %s", c->device,
+                    hipGetErrorString(e));
     }
-    const double n = (double)c->geo.n;
-    const bool shifted = c->cfg.precision != LB_FP64;
-    const double4 base = shifted ? double4{n, 0.0, 0.0, n} : double4{0.0, 0.0, 0.0, 0.0};
-    const int64_t nparts = c->fused_audit_valid ? c->audit_parts : c->nblocks;
-    hipLaunchKernelGGL(k_audit_final, dim3(1), dim3(BLOCK), 0, c->stream, (const double*)c->partials, nparts, base,
-                       c->totals);
-    int rc = launch_status(c, "lb_audit: final");
-    if (rc != LB_OK) return rc;
-    rc = check_hip(c, hipMemcpyAsync(out, c->totals, 4 * sizeof(double), hipMemcpyDeviceToHost, c->stream),
-                   "lb_audit: copy");
-    if (rc != LB_OK) return rc;
-    rc = check_hip(c, hipStreamSynchronize(c->stream), "lb_audit: synchronize");
-    if (rc != LB_OK) return rc;
-    for (int i = 0; i < 4; ++i)
-        if (!std::isfinite(out[i])) return fail(c, LB_ENONFINITE, "lb_audit: total %d is not finite", i);
-    return LB_OK;
+    double* partials = (double*)c->static_scratch;
+    double* totals = partials + 4 * c->nblocks;
+    return audit_into(c, partials, totals, false, out, "lb_audit_static");
 }
 
 int lb_set_surrogate(lb_ctx* c, const lb_mlp* m, double threshold)

@@ -66,6 +66,7 @@ _SIGNATURES = {
     "lb_get_populations": (ctypes.c_int, [_VP, _VP]),
     "lb_set_populations": (ctypes.c_int, [_VP, _VP]),
     "lb_audit": (ctypes.c_int, [_VP, ctypes.POINTER(_D)]),
+    "lb_audit_static": (ctypes.c_int, [_VP, ctypes.POINTER(_D)]),
     "lb_current_buffer": (ctypes.c_int, [_VP]),
     "lb_steps_done": (_I64, [_VP]),
     "lb_destroy": (None, [_VP]),
@@ -179,6 +180,16 @@ def lb_audit(ctx) -> np.ndarray:
     if rc == LB_ENONFINITE:
         raise LBNonFinite(rc, lib().lb_last_error(ctx).decode(), vals)
     _check(rc, ctx, "lb_audit")
+    return vals
+
+
+def lb_audit_static(ctx) -> np.ndarray:
+    out = (ctypes.c_double * 4)()
+    rc = lib().lb_audit_static(ctx, out)
+    vals = np.array(list(out))
+    if rc == LB_ENONFINITE:
+        raise LBNonFinite(rc, lib().lb_last_error(ctx).decode(), vals)
+    _check(rc, ctx, "lb_audit_static")
     return vals
 
 
