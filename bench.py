@@ -36,6 +36,11 @@ NPAIRS = 10_000_000
 PAIR_SEED, INIT_SEED, ORDER_SEED = 11, 5, 17
 EPOCHS, BATCH, LR = 32, 8192, 3e-3
 THRESHOLD = 5e-5
+# Step counts of the accuracy runs, fixed by the workloads themselves (not by
+# --steps): 1000 steps on the 2048 x 2048 lattices, 500 on 8192 x 8192.
+ERR_STEPS_2048 = 1000
+ERR_STEPS_8192 = 500
+HEADLINE_REPEATS = 5
 # MFMA work of one site (37-128-128-37, multiply-adds counted as 2 flops).
 MLP_FLOP_PER_SITE = 2 * (37 * 128 + 128 * 128 + 128 * 37)
 BF16_PEAK_TFLOPS = 2500.0
@@ -104,13 +109,25 @@ def traffic_entry(kernel: str, per_launch_sites: int, field: str = "hbm_bytes_pe
     return k.get(field)
 
 
-def cpu_baseline(seconds_target: float = 12.0):
-    """The FP64 oracle (plain C, one thread) on a bounded sample of the same
-    workload: a 512 x 512 window of the shear-wave state."""
-    from oracle import lbm
-    from paper_1804_01918_amd import inputs
-    lx, ly = 512, 512
-    f = lbm.init(*inputs.shear_wave(lx, ly, seed=0))
+def _cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def _host_threads() -> int:
+    env = os.environ.get("OMP_NUM_THREADS", "")
+    visible = len(os.sched_getaffinity(0))
+    return max(1, min(int(env), visible) if env.isdigit() and int(env) > 0 else visible)
+
+
+def _oracle_mlups(lbm, inputs, n: int, seconds_target: float):
+    f = lbm.init(*inputs.shear_wave(n, n, seed=0))
     t0 = time.perf_counter()
     f = lbm.run(f, TAU, 1)
     one = time.perf_counter() - t0
@@ -118,8 +135,30 @@ def cpu_baseline(seconds_target: float = 12.0):
     t0 = time.perf_counter()
     lbm.run(f, TAU, steps)
     dt = time.perf_counter() - t0
-    return {"value": lx * ly * steps / dt / 1e6, "unit": "MLUPS", "cores": 1, "kind": "oracle",
-            "sample": f"FP64 oracle, {lx}x{ly} shear-wave lattice, {steps} steps, 1 thread, {dt:.1f} s"}
+    return n * n * steps / dt / 1e6, steps, dt
+
+
+def cpu_baseline(seconds_target: float = 10.0):
+    """The FP64 oracle (plain C, the same source built once) on bounded samples
+    of the same workload, on the host's cores: one thread on a 512 x 512
+    window of the shear-wave state, and all the threads the process may use
+    (OpenMP over lattice columns) on a 1024 x 1024 window."""
+    from oracle import lbm
+    from paper_1804_01918_amd import inputs
+    nthreads = _host_threads()
+    try:
+        lbm.set_threads(1)
+        m1, s1, t1 = _oracle_mlups(lbm, inputs, 512, seconds_target)
+        lbm.set_threads(nthreads)
+        mn, sn, tn = _oracle_mlups(lbm, inputs, 1024, seconds_target)
+    finally:
+        lbm.set_threads(1)
+    return {"value": mn, "unit": "MLUPS", "cores": nthreads, "kind": "oracle",
+            "sample": f"FP64 oracle, 1024x1024 shear-wave lattice, {sn} steps, {nthreads} threads "
+                      f"(OpenMP over columns), {tn:.1f} s",
+            "single_thread": {"value": m1, "unit": "MLUPS", "cores": 1,
+                              "sample": f"FP64 oracle, 512x512 shear-wave lattice, {s1} steps, 1 thread, {t1:.1f} s"},
+            "cpu_model": _cpu_model(), "host_cpus_visible": len(os.sched_getaffinity(0))}
 
 
 def train_network(torch, lb, train: bool = True):
@@ -152,23 +191,25 @@ def learned_variant(args, torch, lb, inputs, run, counts, nsites, shear_ref, rt_
     from paper_1804_01918_amd.roofline import HBM_PEAK_GBS, bytes_per_site
     net, training = train_network(torch, lb)
     counts.clear()
-    dt, mom = run("f32s", "caosoa", args.steps, args.warmup, keep=True, net=net)
-    m = nsites * args.steps / dt / 1e6
-    v = {"mlups": m, "ms_per_step": dt / args.steps * 1e3, "threshold": THRESHOLD,
+    timed = ERR_STEPS_2048 - args.warmup
+    dt, mom = run("f32s", "caosoa", timed, args.warmup, keep=True, net=net)
+    m = nsites * timed / dt / 1e6
+    v = {"mlups": m, "ms_per_step": dt / timed * 1e3, "timed_steps": timed, "threshold": THRESHOLD,
          "fallback_fraction": counts.get("fallback_fraction"),
          "mfma_tflops": m * 1e6 * MLP_FLOP_PER_SITE / 1e12,
          "mfma_frac": m * 1e6 * MLP_FLOP_PER_SITE / 1e12 / BF16_PEAK_TFLOPS,
          "hbm_frac": m * 1e6 * bytes_per_site("f32") / (HBM_PEAK_GBS * 1e9),
          "hbm_traffic_bytes_per_launch": traffic_entry("k_step_learned_f32s_caosoa_2048x2048", nsites),
          "algorithmic_bytes_per_launch": bytes_per_site("f32") * nsites,
-         "error_vs_f64_after_steps": args.steps + args.warmup,
+         "error_vs_f64_after_steps": ERR_STEPS_2048,
          "field_error_vs_f64": field_errors(shear_ref, mom) if shear_ref is not None else None,
          "training": training}
     if rt_ref is not None:
         rt = (LX, LY, [torch.from_numpy(a).cuda() for a in inputs.rayleigh_taylor(LX, LY, seed=0)])
         counts.clear()
-        _, mom = run("f32s", "caosoa", args.steps, args.warmup, keep=True, state=rt, net=net)
-        v["rayleigh_taylor_2048"] = {"fallback_fraction": counts.get("fallback_fraction"),
+        _, mom = run("f32s", "caosoa", timed, args.warmup, keep=True, state=rt, net=net)
+        v["rayleigh_taylor_2048"] = {"error_vs_f64_after_steps": ERR_STEPS_2048,
+                                     "fallback_fraction": counts.get("fallback_fraction"),
                                      "field_error_vs_f64": field_errors(rt_ref, mom)}
     return v, net
 
@@ -286,10 +327,13 @@ def scale_variant(args, torch, inputs, run, counts, net):
     learned collide on the same GPU, errors against the FP64 run."""
     n = 8192
     state = (n, n, [torch.from_numpy(a).cuda() for a in inputs.rayleigh_taylor(n, n, seed=0)])
-    steps, warm = args.scale_steps, args.warmup
-    out = {"lattice": [n, n], "steps": steps + warm, "timed_steps": steps}
+    warm = args.warmup
+    steps = args.scale_steps - warm
+    out = {"lattice": [n, n], "steps": steps + warm, "error_vs_f64_after_steps": steps + warm,
+           "timed_steps": steps}
     dt, ref = run("f64", "caosoa", steps, warm, keep=True, state=state)
-    out["f64"] = {"mlups": n * n * steps / dt / 1e6}
+    out["f64"] = {"mlups": n * n * steps / dt / 1e6,
+                  "hbm_frac": n * n * steps / dt * 592 / 8e12}
     dt, mom = run("f32s", "caosoa", steps, warm, keep=True, state=state)
     out["f32s"] = {"mlups": n * n * steps / dt / 1e6, "field_error_vs_f64": field_errors(ref, mom)}
     dt, mom = run("f16s", "caosoa", steps, warm, keep=True, state=state)
@@ -318,7 +362,8 @@ def main():
                     help="with --only learned: skip the training (counter runs; HBM bytes do not depend on it)")
     ap.add_argument("--no-scale", action="store_true")
     ap.add_argument("--no-energy", action="store_true")
-    ap.add_argument("--scale-steps", type=int, default=500)
+    ap.add_argument("--scale-steps", type=int, default=ERR_STEPS_8192,
+                    help="total steps (warm-up included) of the 8192 x 8192 runs")
     ap.add_argument("--only", default=None, help="precision:layout[:split], or 'learned', to time alone")
     ap.add_argument("--copy-bytes", type=int, default=0,
                     help="only run the library's copy kernel on buffers of this size (counter calibration)")
@@ -379,8 +424,15 @@ def main():
                           "ms_per_step": dt / args.steps * 1e3}))
         return
 
-    # Headline: FP64 CAoSoA fused.
-    dt, ref_mom = run("f64", "caosoa", args.steps, args.warmup, keep=True)
+    # Headline: FP64 CAoSoA fused, the median of HEADLINE_REPEATS timed runs
+    # of exactly --steps steps each (after --warmup untimed steps).
+    lat = lb.Lattice(LX, LY, TAU, fields, precision="f64", layout="caosoa", audit=True)
+    lat.step(args.warmup)
+    head = sorted(timed_steps(lat, torch, args.steps) for _ in range(HEADLINE_REPEATS))
+    lat.close()
+    del lat
+    torch.cuda.empty_cache()
+    dt = head[HEADLINE_REPEATS // 2]
     mlups = nsites * args.steps / dt / 1e6
     t_launch = dt / args.steps
     alg_bytes = bytes_per_site("f64", fused=True) * nsites
@@ -394,7 +446,9 @@ def main():
         "config": {"workload": "D2Q37 2048x2048 periodic shear wave (u_x=0.05 sin(2 pi y/LY) + 1e-4 noise), "
                                "FP64 populations, CAoSoA layout, fused propagate+collide, tau=0.8",
                    "lattice": [LX, LY], "precision": "f64", "layout": "caosoa", "fused": True, "tau": TAU,
-                   "audit": "FP64 mass/momentum/energy sums fused into the last timed step"},
+                   "audit": "FP64 mass/momentum/energy sums fused into the last step of each timed run",
+                   "value_is": f"median of {HEADLINE_REPEATS} timed runs of {args.steps} steps each"},
+        "headline_repeats_mlups": [nsites * args.steps / d / 1e6 for d in head],
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                      "kernel": "k_step<PrecF64, Layout<CAoSoA>> (fused propagate+collide)",
@@ -407,27 +461,34 @@ def main():
         tf = fps * nsites / t_launch / 1e12
         out["collide_vector_flops"] = {"flops_per_site": fps, "achieved_tflops": tf, "fp64_vector_peak_tflops": 78.6,
                                        "frac": tf / 78.6, "source": "SQ_INSTS_VALU_{FMA,MUL,ADD,TRANS}_F64 counters"}
+    # FP64 reference of the accuracy runs: the shear wave after exactly
+    # ERR_STEPS_2048 steps (the workload's own count, whatever --steps is).
+    err_timed = ERR_STEPS_2048 - args.warmup
+    ref_mom = None
+    if not (args.no_variants and args.no_learned):
+        _, ref_mom = run("f64", "caosoa", err_timed, args.warmup, keep=True)
+    rt_ref = None
     if not args.no_variants:
         variants = {}
         vs = args.variant_steps
         for prec in ("f32s", "f16s"):
-            dtv, mom = run(prec, "caosoa", args.steps, args.warmup, keep=True)
-            m = nsites * args.steps / dtv / 1e6
+            dtv, mom = run(prec, "caosoa", err_timed, args.warmup, keep=True)
+            m = nsites * err_timed / dtv / 1e6
             variants[f"{prec}_caosoa_fused"] = {
                 "compensated_moment_sums": prec == "f32s",
-                "mlups": m, "ms_per_step": dtv / args.steps * 1e3,
+                "mlups": m, "ms_per_step": dtv / err_timed * 1e3, "timed_steps": err_timed,
                 "hbm_frac": m * 1e6 * bytes_per_site(prec[:3]) / (HBM_PEAK_GBS * 1e9),
-                "error_vs_f64_after_steps": args.steps + args.warmup,
+                "error_vs_f64_after_steps": ERR_STEPS_2048,
                 "field_error_vs_f64": field_errors(ref_mom, mom),
                 "hbm_traffic_bytes_per_launch": traffic_entry(f"k_step_{prec}_caosoa_2048x2048", nsites),
                 "algorithmic_bytes_per_launch": bytes_per_site(prec[:3]) * nsites}
         # the same FP32 step with plain (uncompensated) moment sums
-        dtv, mom = run("f32s", "caosoa", args.steps, args.warmup, keep=True, compensated=False)
-        m = nsites * args.steps / dtv / 1e6
+        dtv, mom = run("f32s", "caosoa", err_timed, args.warmup, keep=True, compensated=False)
+        m = nsites * err_timed / dtv / 1e6
         variants["f32s_caosoa_fused_uncompensated"] = {
             "compensated_moment_sums": False, "mlups": m,
             "hbm_frac": m * 1e6 * bytes_per_site("f32") / (HBM_PEAK_GBS * 1e9),
-            "error_vs_f64_after_steps": args.steps + args.warmup, "field_error_vs_f64": field_errors(ref_mom, mom)}
+            "error_vs_f64_after_steps": ERR_STEPS_2048, "field_error_vs_f64": field_errors(ref_mom, mom)}
         for layout in ("soa", "aos", "csoa"):
             dtv, _ = run("f64", layout, vs, args.warmup)
             m = nsites * vs / dtv / 1e6
@@ -436,12 +497,6 @@ def main():
             dtv, _ = run("f64", layout, vs, args.warmup, split=True)
             m = nsites * vs / dtv / 1e6
             variants[f"f64_{layout}_split"] = {"mlups": m, "hbm_frac": m * 1e6 * 1184 / (HBM_PEAK_GBS * 1e9)}
-        # spread of the headline: three more timed runs of the same workload
-        reps = []
-        for _ in range(3):
-            dtr, _ = run("f64", "caosoa", args.steps, args.warmup)
-            reps.append(nsites * args.steps / dtr / 1e6)
-        variants["f64_caosoa_fused_repeats_mlups"] = reps
         cb = copy_bandwidth(torch, lb, alg_bytes // 2)
         variants["copy_kernel_gbs"] = cb
         out["roofline"]["frac_of_copy"] = achieved / cb
@@ -450,24 +505,30 @@ def main():
 
         # Precision on the thermal Rayleigh-Taylor-like state.
         rt = (LX, LY, [torch.from_numpy(a).cuda() for a in inputs.rayleigh_taylor(LX, LY, seed=0)])
-        nrt = args.steps + args.warmup
-        _, rt_ref = run("f64", "caosoa", args.steps, args.warmup, keep=True, state=rt)
-        variants["rayleigh_taylor_2048"] = {"steps": nrt}
+        _, rt_ref = run("f64", "caosoa", err_timed, args.warmup, keep=True, state=rt)
+        variants["rayleigh_taylor_2048"] = {"error_vs_f64_after_steps": ERR_STEPS_2048}
         for prec in ("f32s", "f16s"):
-            _, mom = run(prec, "caosoa", args.steps, args.warmup, keep=True, state=rt)
+            _, mom = run(prec, "caosoa", err_timed, args.warmup, keep=True, state=rt)
             variants["rayleigh_taylor_2048"][f"{prec}_field_error_vs_f64"] = field_errors(rt_ref, mom)
-        _, mom = run("f32s", "caosoa", args.steps, args.warmup, keep=True, state=rt, compensated=False)
+        _, mom = run("f32s", "caosoa", err_timed, args.warmup, keep=True, state=rt, compensated=False)
         variants["rayleigh_taylor_2048"]["f32s_uncompensated_field_error_vs_f64"] = field_errors(rt_ref, mom)
         out["variants"] = variants
 
     if not args.no_learned:
         out["variants"] = out.get("variants", {})
-        lv, net = learned_variant(args, torch, lb, inputs, run, counts, nsites, ref_mom, rt_ref if not args.no_variants else None)
+        lv, net = learned_variant(args, torch, lb, inputs, run, counts, nsites, ref_mom, rt_ref)
         lv["mlups_vs_f32s_plain"] = (lv["mlups"] / out["variants"]["f32s_caosoa_fused"]["mlups"]
                                      if "f32s_caosoa_fused" in out["variants"] else None)
         out["variants"]["learned_f32s_caosoa_fused"] = lv
         if not args.no_scale:
-            out["variants"]["scale_8192_rayleigh_taylor"] = scale_variant(args, torch, inputs, run, counts, net)
+            sv = scale_variant(args, torch, inputs, run, counts, net)
+            out["variants"]["scale_8192_rayleigh_taylor"] = sv
+            out["largest_single_gpu_config"] = {
+                "workload": "D2Q37 8192x8192 periodic Rayleigh-Taylor-like state, FP64 populations, CAoSoA, "
+                            "fused propagate+collide, tau=0.8",
+                "steps": sv["steps"], "timed_steps": sv["timed_steps"], "f64_mlups": sv["f64"]["mlups"],
+                "f64_hbm_frac": sv["f64"]["hbm_frac"], "f32s_mlups": sv["f32s"]["mlups"],
+                "f16s_mlups": sv["f16s"]["mlups"], "learned_f32s_mlups": sv["learned_f32s"]["mlups"]}
         if not args.no_energy:
             out["variants"]["energy_2048"] = energy_variant(args, torch, lb, fields, net)
         net.close()

@@ -14,7 +14,9 @@ SRC = os.path.join(HERE, "lb_oracle.c")
 LIB = os.path.join(HERE, "_lb_oracle.so")
 
 # Plain IEEE binary64: no contraction into FMA, no fast-math, scalar code.
-CFLAGS = ["-O2", "-std=c99", "-fPIC", "-shared", "-ffp-contract=off", "-fno-fast-math"]
+# OpenMP only runs the column loops on several host threads (all-core
+# baseline); the thread count is 1 unless the caller sets it.
+CFLAGS = ["-O2", "-std=c99", "-fPIC", "-shared", "-ffp-contract=off", "-fno-fast-math", "-fopenmp"]
 
 
 def build(force: bool = True) -> str:

@@ -29,7 +29,11 @@
  * weights w, both from the quadrature solve in lattice.py).
  *
  * Plain loops, no blocking, fusion or reordering: each function follows the
- * definition as written above.
+ * definition as written above. The loops over lattice columns x of init,
+ * propagate and collide may run on several host threads (OpenMP, for the
+ * all-core CPU baseline): every site's result is computed by the same code
+ * from the same inputs whichever thread runs it, so the result does not
+ * depend on the thread count. The audit sums stay on one thread, in order.
  */
 #include <math.h>
 #include <stddef.h>
@@ -38,6 +42,12 @@
 
 #define Q 37
 #define DIM 2
+
+/* Host threads of the column loops; 1 unless orc_set_threads is called. */
+static int orc_threads = 1;
+
+void orc_set_threads(int n) { orc_threads = n > 0 ? n : 1; }
+int orc_get_threads(void) { return orc_threads; }
 
 static double kd(int a, int b) { return a == b ? 1.0 : 0.0; }
 
@@ -158,9 +168,10 @@ static int wrap(long v, int n)
 void orc_init(int lx, int ly, const double *xi, const double *w, const double *rho,
               const double *ux, const double *uy, const double *T, double *f)
 {
-    double feq[Q];
+#pragma omp parallel for num_threads(orc_threads) schedule(static)
     for (int x = 0; x < lx; ++x)
         for (int y = 0; y < ly; ++y) {
+            double feq[Q];
             const size_t s = (size_t)x * ly + y;
             orc_feq_site(xi, w, rho[s], ux[s], uy[s], T[s], feq);
             for (int p = 0; p < Q; ++p) f[at(p, x, y, lx, ly)] = feq[p];
@@ -170,8 +181,9 @@ void orc_init(int lx, int ly, const double *xi, const double *w, const double *r
 /* Pull propagate: dst[p][x][y] = src[p][x - cx_p][y - cy_p], periodic. c is (37, 2). */
 void orc_propagate(int lx, int ly, const int64_t *c, const double *src, double *dst)
 {
-    for (int p = 0; p < Q; ++p)
-        for (int x = 0; x < lx; ++x)
+#pragma omp parallel for num_threads(orc_threads) schedule(static)
+    for (int x = 0; x < lx; ++x)
+        for (int p = 0; p < Q; ++p)
             for (int y = 0; y < ly; ++y) {
                 const int sx = wrap((long)x - c[DIM * p], lx);
                 const int sy = wrap((long)y - c[DIM * p + 1], ly);
@@ -182,9 +194,10 @@ void orc_propagate(int lx, int ly, const int64_t *c, const double *src, double *
 /* Collide every site in place. */
 void orc_collide(int lx, int ly, const double *xi, const double *w, double tau, double *f)
 {
-    double site[Q];
+#pragma omp parallel for num_threads(orc_threads) schedule(static)
     for (int x = 0; x < lx; ++x)
         for (int y = 0; y < ly; ++y) {
+            double site[Q];
             for (int p = 0; p < Q; ++p) site[p] = f[at(p, x, y, lx, ly)];
             orc_collide_site(xi, w, tau, site);
             for (int p = 0; p < Q; ++p) f[at(p, x, y, lx, ly)] = site[p];

@@ -32,10 +32,24 @@ def _lib():
     lib.orc_run.argtypes = [i, i, _I64, _D, _D, d, i, _D, _D]
     lib.orc_moments.argtypes = [i, i, _D, _D, _D, _D, _D, _D]
     lib.orc_audit.argtypes = [i, i, _D, _D, _D]
+    lib.orc_set_threads.argtypes = [i]
+    lib.orc_set_threads.restype = None
+    lib.orc_get_threads.argtypes = []
+    lib.orc_get_threads.restype = i
     for fn in (lib.orc_feq_site, lib.orc_moments_site, lib.orc_collide_site, lib.orc_init,
                lib.orc_propagate, lib.orc_collide, lib.orc_run, lib.orc_moments, lib.orc_audit):
         fn.restype = None
     return lib
+
+
+def set_threads(n: int) -> None:
+    """Host threads for the column loops of init, propagate and collide
+    (results do not depend on it)."""
+    _lib().orc_set_threads(int(n))
+
+
+def get_threads() -> int:
+    return _lib().orc_get_threads()
 
 
 def _p(a: np.ndarray, t=_D):

@@ -81,3 +81,21 @@ def test_run_window_matches_periodic_run(lx, ly, n):
     got = lbm.run_window(fields, sites, n, 0.8)
     for k, (x, y) in enumerate(sites):
         assert np.array_equal(got[k], full[:, x, y])
+
+
+def test_threaded_oracle_is_bit_identical_to_one_thread():
+    """The all-core build of the oracle (column loops on several threads)
+    gives the one-thread result bit for bit: init, propagate and collide are
+    per site."""
+    from oracle import lbm
+    from paper_1804_01918_amd import inputs
+    fields = inputs.random_equilibrium(45, 38, seed=4)
+    try:
+        lbm.set_threads(1)
+        one = lbm.run(lbm.init(*fields), 0.7, 3)
+        lbm.set_threads(4)
+        assert lbm.get_threads() == 4
+        many = lbm.run(lbm.init(*fields), 0.7, 3)
+    finally:
+        lbm.set_threads(1)
+    assert np.array_equal(one.view(np.uint64), many.view(np.uint64))
