@@ -250,3 +250,129 @@ void orc_audit(int lx, int ly, const double *xi, const double *f, double *out)
     out[2] = py;
     out[3] = e;
 }
+
+/* ---- Body force and walls ----------------------------------------------
+ *
+ * The paper's production runs (Section 3) follow a Rayleigh-Taylor system:
+ * a fluid under gravity between a bottom and a top wall, the "Global"
+ * timings of Section 5 including the kernels that apply them. The paper
+ * defines neither, so these are the readings taken:
+ *
+ * Force (acceleration g per time step, thermal units): the equilibrium of
+ * the collide is taken at a shifted velocity and temperature,
+ *   u_s = u + tau g,  T_s = T + tau (1 - tau) |g|^2 / 2,
+ *   f_i <- f_i - (f_i - f_eq_i(rho, u_s, T_s)) / tau.
+ * The velocity shift is Shan and Chen's (Phys. Rev. E 47, 1815, 1993); the
+ * temperature shift is fixed by energy: with the equilibrium's exact
+ * moments, one step changes rho by 0, rho u by rho g and the energy
+ * (1/2) sum f xi^2 by rho (u.g + |g|^2 / 2), the work of the force.
+ *
+ * Walls: diffuse reflection (Ansumali and Karlin, Phys. Rev. E 66, 026311,
+ * 2002) on the planes y = -1/2 (bottom, temperature t_bottom) and
+ * y = LY - 1/2 (top, t_top), at rest; x stays periodic. In the pull
+ * propagate, a population whose source row y - c_y lies beyond a wall is
+ * emitted by that wall: f_eq_p(rho_w(x_s), 0, T_w) with x_s = x - c_x the
+ * source column. rho_w of a column makes the wall emit from it exactly the
+ * mass that left the fluid towards the wall from that column in the same
+ * propagate: the populations with c_y < 0 (bottom) in rows y < -c_y, or
+ * c_y > 0 (top) in rows y >= LY - c_y. With K_w = sum over the populations
+ * moving away from the wall of |c_y| f_eq_p(1, 0, T_w) (each is emitted
+ * into |c_y| rows), rho_w = (outgoing mass of the column) / K_w. Total mass
+ * is conserved exactly.
+ */
+
+/* Forced BGK collision of one site, in place. */
+void orc_collide_site_force(const double *xi, const double *w, double tau, double gx, double gy, double *f)
+{
+    double rho, ux, uy, T, feq[Q];
+    orc_moments_site(f, xi, &rho, &ux, &uy, &T);
+    const double us_x = ux + tau * gx;
+    const double us_y = uy + tau * gy;
+    const double Ts = T + tau * (1.0 - tau) * (gx * gx + gy * gy) / 2.0;
+    orc_feq_site(xi, w, rho, us_x, us_y, Ts, feq);
+    for (int i = 0; i < Q; ++i) f[i] = f[i] - (f[i] - feq[i]) / tau;
+}
+
+/* Forced collide of every site in place. */
+void orc_collide_force(int lx, int ly, const double *xi, const double *w, double tau, double gx, double gy,
+                       double *f)
+{
+#pragma omp parallel for num_threads(orc_threads) schedule(static)
+    for (int x = 0; x < lx; ++x)
+        for (int y = 0; y < ly; ++y) {
+            double site[Q];
+            for (int p = 0; p < Q; ++p) site[p] = f[at(p, x, y, lx, ly)];
+            orc_collide_site_force(xi, w, tau, gx, gy, site);
+            for (int p = 0; p < Q; ++p) f[at(p, x, y, lx, ly)] = site[p];
+        }
+}
+
+/* Wall densities rho_w[x] of one wall (bottom: side = 0, top: side = 1) from
+ * the state src before propagation. */
+static void wall_density(int lx, int ly, const int64_t *c, const double *xi, const double *w, int side,
+                         double t_wall, const double *src, double *rho_w)
+{
+    double unit[Q];
+    orc_feq_site(xi, w, 1.0, 0.0, 0.0, t_wall, unit);
+    double K = 0.0;
+    for (int p = 0; p < Q; ++p) {
+        const long cy = (long)c[DIM * p + 1];
+        if (side == 0 && cy > 0) K += (double)cy * unit[p];
+        if (side == 1 && cy < 0) K += (double)(-cy) * unit[p];
+    }
+    for (int x = 0; x < lx; ++x) {
+        double out = 0.0;
+        for (int p = 0; p < Q; ++p) {
+            const long cy = (long)c[DIM * p + 1];
+            for (int y = 0; y < ly; ++y) {
+                const int leaves = side == 0 ? (cy < 0 && y + cy < 0) : (cy > 0 && y + cy >= ly);
+                if (leaves) out += src[at(p, x, y, lx, ly)];
+            }
+        }
+        rho_w[x] = out / K;
+    }
+}
+
+/* Pull propagate with diffuse walls at y = -1/2 and y = LY - 1/2, periodic
+ * in x. rho_w is scratch of 2 * lx doubles. */
+void orc_propagate_walls(int lx, int ly, const int64_t *c, const double *xi, const double *w, double t_bottom,
+                         double t_top, const double *src, double *dst, double *rho_w)
+{
+    double *rho_b = rho_w, *rho_t = rho_w + lx;
+    wall_density(lx, ly, c, xi, w, 0, t_bottom, src, rho_b);
+    wall_density(lx, ly, c, xi, w, 1, t_top, src, rho_t);
+#pragma omp parallel for num_threads(orc_threads) schedule(static)
+    for (int x = 0; x < lx; ++x)
+        for (int p = 0; p < Q; ++p)
+            for (int y = 0; y < ly; ++y) {
+                const int sx = wrap((long)x - c[DIM * p], lx);
+                const long sy = (long)y - c[DIM * p + 1];
+                double v;
+                if (sy < 0 || sy >= ly) {
+                    double feq[Q];
+                    if (sy < 0) orc_feq_site(xi, w, rho_b[sx], 0.0, 0.0, t_bottom, feq);
+                    else orc_feq_site(xi, w, rho_t[sx], 0.0, 0.0, t_top, feq);
+                    v = feq[p];
+                } else {
+                    v = src[at(p, sx, (int)sy, lx, ly)];
+                }
+                dst[at(p, x, y, lx, ly)] = v;
+            }
+}
+
+/* nsteps x (propagate; collide) with a body force g and, if walls != 0,
+ * diffuse walls at the bottom and top. tmp is a second buffer of the size of
+ * f, rho_w scratch of 2 * lx doubles. With g = 0 and walls = 0 this is
+ * orc_run. */
+void orc_run_bc(int lx, int ly, const int64_t *c, const double *xi, const double *w, double tau, double gx,
+                double gy, int walls, double t_bottom, double t_top, int nsteps, double *f, double *tmp,
+                double *rho_w)
+{
+    const size_t n = (size_t)Q * lx * ly;
+    for (int s = 0; s < nsteps; ++s) {
+        if (walls) orc_propagate_walls(lx, ly, c, xi, w, t_bottom, t_top, f, tmp, rho_w);
+        else orc_propagate(lx, ly, c, f, tmp);
+        orc_collide_force(lx, ly, xi, w, tau, gx, gy, tmp);
+        memcpy(f, tmp, n * sizeof(double));
+    }
+}

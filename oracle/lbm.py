@@ -32,6 +32,12 @@ def _lib():
     lib.orc_run.argtypes = [i, i, _I64, _D, _D, d, i, _D, _D]
     lib.orc_moments.argtypes = [i, i, _D, _D, _D, _D, _D, _D]
     lib.orc_audit.argtypes = [i, i, _D, _D, _D]
+    lib.orc_collide_site_force.argtypes = [_D, _D, d, d, d, _D]
+    lib.orc_collide_force.argtypes = [i, i, _D, _D, d, d, d, _D]
+    lib.orc_propagate_walls.argtypes = [i, i, _I64, _D, _D, d, d, _D, _D, _D]
+    lib.orc_run_bc.argtypes = [i, i, _I64, _D, _D, d, d, d, i, d, d, i, _D, _D, _D]
+    for fn in (lib.orc_collide_site_force, lib.orc_collide_force, lib.orc_propagate_walls, lib.orc_run_bc):
+        fn.restype = None
     lib.orc_set_threads.argtypes = [i]
     lib.orc_set_threads.restype = None
     lib.orc_get_threads.argtypes = []
@@ -121,6 +127,48 @@ def run(f: np.ndarray, tau: float, nsteps: int) -> np.ndarray:
     _, lx, ly = out.shape
     tmp = np.empty_like(out)
     _lib().orc_run(lx, ly, _p(c, _I64), _p(xi), _p(w), tau, nsteps, _p(out), _p(tmp))
+    return out
+
+
+def collide_site_force(f: np.ndarray, tau: float, g) -> np.ndarray:
+    """Forced BGK collision of one site (equilibrium at u + tau g and
+    T + tau (1 - tau) |g|^2 / 2)."""
+    xi, w, _ = _tables()
+    out = _f64(f).copy()
+    _lib().orc_collide_site_force(_p(xi), _p(w), tau, float(g[0]), float(g[1]), _p(out))
+    return out
+
+
+def collide_force(f: np.ndarray, tau: float, g) -> np.ndarray:
+    xi, w, _ = _tables()
+    out = _f64(f).copy()
+    _, lx, ly = out.shape
+    _lib().orc_collide_force(lx, ly, _p(xi), _p(w), tau, float(g[0]), float(g[1]), _p(out))
+    return out
+
+
+def propagate_walls(f: np.ndarray, t_bottom: float, t_top: float) -> np.ndarray:
+    """Pull propagate, periodic in x, diffuse walls at y = -1/2 (t_bottom)
+    and y = LY - 1/2 (t_top)."""
+    xi, w, c = _tables()
+    f = _f64(f)
+    _, lx, ly = f.shape
+    out = np.empty_like(f)
+    rho_w = np.empty(2 * lx)
+    _lib().orc_propagate_walls(lx, ly, _p(c, _I64), _p(xi), _p(w), t_bottom, t_top, _p(f), _p(out), _p(rho_w))
+    return out
+
+
+def run_bc(f: np.ndarray, tau: float, nsteps: int, g=(0.0, 0.0), walls: bool = False, t_bottom: float = 1.0,
+           t_top: float = 1.0) -> np.ndarray:
+    """nsteps x (propagate, with diffuse walls if `walls`; forced collide)."""
+    xi, w, c = _tables()
+    out = _f64(f).copy()
+    _, lx, ly = out.shape
+    tmp = np.empty_like(out)
+    rho_w = np.empty(2 * lx)
+    _lib().orc_run_bc(lx, ly, _p(c, _I64), _p(xi), _p(w), tau, float(g[0]), float(g[1]), int(bool(walls)),
+                      t_bottom, t_top, nsteps, _p(out), _p(tmp), _p(rho_w))
     return out
 
 
