@@ -85,6 +85,22 @@ typedef struct {
     void *scratch;        /* device, >= lb_scratch_bytes(), 256-byte aligned */
     size_t scratch_bytes; /* size of scratch in bytes */
     void *stream;         /* hipStream_t to launch on; NULL = the null stream */
+    /* Body force and walls (the paper's Rayleigh-Taylor setting, Section 3:
+     * a fluid under gravity between a bottom and a top wall; Section 5 times
+     * the extra kernels that apply them with the step). Zero-initialised
+     * fields give the fully periodic lattice without force. */
+    double gx, gy;        /* acceleration per time step, thermal units, finite, |g| <= 1:
+                             the collide's equilibrium is taken at u + tau g and
+                             T + tau (1 - tau) |g|^2 / 2, so each step adds rho g of
+                             momentum and rho (u.g + |g|^2/2) of energy per site */
+    int32_t walls;        /* 0: periodic in y; 1: diffuse walls at rest on the planes
+                             y = -1/2 (bottom) and y = LY - 1/2 (top), x periodic: a
+                             population pulled from beyond a wall is emitted by it with
+                             the equilibrium at rest at the wall's temperature, the
+                             density of each source column set so that the wall emits
+                             the mass that left the fluid from that column towards it
+                             in the same propagate (mass is conserved) */
+    double t_bottom, t_top; /* wall temperatures when walls = 1: finite, > 0 */
 } lb_config;
 
 typedef struct lb_ctx lb_ctx;
@@ -100,8 +116,9 @@ typedef struct lb_ctx lb_ctx;
 size_t lb_buffer_bytes(int32_t lx, int32_t ly, int32_t precision, int32_t layout);
 
 /* Bytes of scratch a context of this lattice needs: the FP64 partial sums of
- * the audit (4 per 256-site row tile), its 4 totals and the two counters of
- * the learned collide; 0 for an invalid extent. Host only. */
+ * the audit (4 per 256-site row tile), its 4 totals, the two counters of
+ * the learned collide, the walls' equilibrium table and their per-column
+ * densities (2 * lx); 0 for an invalid extent. Host only. */
 size_t lb_scratch_bytes(int32_t lx, int32_t ly);
 
 /* Create a context and set the populations of buf[0] to the equilibrium of
@@ -117,17 +134,22 @@ size_t lb_scratch_bytes(int32_t lx, int32_t ly);
  * precision and layout (LB_EUNSUPPORTED), LY % VL for the clustered layouts
  * (LB_EUNSUPPORTED), non-NULL, distinct, 256-byte-aligned buffers and
  * scratch of at least lb_scratch_bytes() (LB_EINVAL), non-NULL fields
- * (LB_EINVAL). LB_EDEVICE if the launch fails. */
+ * (LB_EINVAL), a finite force with |gx|, |gy| <= 1, walls 0 or 1 and finite
+ * positive wall temperatures (LB_EINVAL). LB_EDEVICE if a launch fails. */
 int lb_init(lb_ctx **out, const lb_config *cfg, const double *rho, const double *ux,
             const double *uy, const double *T);
 
 /* Propagate (paper, Section 3; Listing 1): every population p at site s is
  * replaced by the one at s - c_p (pull gather, periodic), copied bit for bit
- * into the other buffer, which then becomes current. */
+ * into the other buffer, which then becomes current. With walls, the
+ * populations pulled from beyond a wall are the wall's emission (see
+ * lb_config.walls), computed from the current buffer before the gather. */
 int lb_propagate(lb_ctx *ctx);
 
 /* Collide (paper, Section 3): per site, moments, equilibrium and BGK
- * relaxation f <- f - (f - f_eq)/tau, in place on the current buffer. */
+ * relaxation f <- f - (f - f_eq)/tau, in place on the current buffer; with
+ * a body force the equilibrium is taken at the shifted velocity and
+ * temperature of lb_config.gx, gy. */
 int lb_collide(lb_ctx *ctx);
 
 /* nsteps time steps (paper, Section 3: a time step is propagate followed by
@@ -143,8 +165,9 @@ int lb_step(lb_ctx *ctx, int32_t nsteps);
  * velocity and temperature of a site, the moments the collide relaxes
  * around), in FP64 into caller-owned device arrays [lx][ly] each:
  * rho = sum f, rho u = sum f xi, rho (|u|^2 + 2 T) = sum f |xi|^2, with
- * xi = r c the thermal velocities. LB_EINVAL for a NULL context or array.
- * Asynchronous. */
+ * xi = r c the thermal velocities. Under a body force these are the moments
+ * of the stored (post-collision) populations; the velocity half-way through
+ * the step is u - g/2. LB_EINVAL for a NULL context or array. Asynchronous. */
 int lb_moments(lb_ctx *ctx, double *rho, double *ux, double *uy, double *T);
 
 /* Current populations in the canonical FP64 layout (device [37][lx][ly],
@@ -301,7 +324,8 @@ int lb_pairgen(float *pre, float *post, int64_t n, uint64_t seed, double tau, vo
  * its use. Sites with residual > threshold (or outside the training box)
  * fall back to the plain FP32 collide; with threshold 0 every site does and
  * the step equals the plain FP32 step bit for bit. Errors: LB_EUNSUPPORTED
- * for FP64 or FP16 storage; LB_EINVAL for a negative or non-finite threshold
+ * for FP64 or FP16 storage, or for a lattice with walls or a body force;
+ * LB_EINVAL for a negative or non-finite threshold
  * or a lattice of more than 2^32 - 1 sites; LB_EDEVICE if the device cannot
  * be queried. No device memory is allocated. (Not in the paper: the learned
  * collide is an addition to its method.) */

@@ -197,10 +197,33 @@ __device__ inline void relax_emit(const C (&v)[Q], const Macro<C>& s, C omega, C
     }
 }
 
-// BGK collide of one site held in registers; emit(p, value) receives the
-// post-collision populations.
-template <class P, bool COMP, class Emit>
-__device__ inline void collide_site(const typename P::C (&v)[Q], typename P::C omega, Emit&& emit)
+// Body force g (acceleration per step, thermal units): the collide relaxes
+// towards the equilibrium at the shifted velocity u + tau g and temperature
+// T + tau (1 - tau) |g|^2 / 2 (a velocity shift of the equilibrium, with the
+// temperature shift that makes the energy gain exactly the work of the
+// force). Per step a site keeps its mass, gains rho g of momentum and
+// rho (u.g + |g|^2 / 2) of energy. Held as the shifts of (Ux, Uy) = R u and
+// of t = T - 1; zero shifts leave every rounding of the plain collide as is.
+template <typename C>
+struct Force {
+    C dUx, dUy;  // R tau g
+    C dt;        // tau (1 - tau) |g|^2 / 2
+};
+
+template <typename C>
+__device__ inline void apply_force(Macro<C>& s, const Force<C>& f)
+{
+    s.Ux += f.dUx;
+    s.Uy += f.dUy;
+    s.u2 = mulk(s.Ux * s.Ux + s.Uy * s.Uy, THETA);
+    s.t += f.dt;
+}
+
+// BGK collide of one site held in registers, with a body force if FORCE;
+// emit(p, value) receives the post-collision populations.
+template <class P, bool COMP, bool FORCE, class Emit>
+__device__ inline void collide_site_f(const typename P::C (&v)[Q], typename P::C omega,
+                                      const Force<typename P::C>& force, Emit&& emit)
 {
     using C = typename P::C;
     RawMoments<C> m;
@@ -208,8 +231,15 @@ __device__ inline void collide_site(const typename P::C (&v)[Q], typename P::C o
         m = raw_moments_compensated(v);
     else
         m = raw_moments_plain(v);
-    const Macro<C> s = macro_from_raw<C, P::shifted>(m);
+    Macro<C> s = macro_from_raw<C, P::shifted>(m);
+    if constexpr (FORCE) apply_force(s, force);
     relax_emit<C, P::shifted>(v, s, omega, C(1) - omega, emit);
+}
+
+template <class P, bool COMP, class Emit>
+__device__ inline void collide_site(const typename P::C (&v)[Q], typename P::C omega, Emit&& emit)
+{
+    collide_site_f<P, COMP, false>(v, omega, Force<typename P::C>{}, emit);
 }
 
 // Equilibrium (plain f_eq or shifted g_eq) from FP64 fields, in FP64.

@@ -102,6 +102,116 @@ __device__ inline void block_reduce4(double (&acc)[4], double* out)
     }
 }
 
+// ---- walls and body force -------------------------------------------------
+// Diffuse walls at rest on the planes y = -1/2 (wall 0, bottom) and
+// y = LY - 1/2 (wall 1, top), each at its own temperature; x stays periodic.
+// In the pull propagate a population whose source row lies beyond a wall is
+// emitted by that wall: the equilibrium at rest and the wall's temperature,
+// with the density rho_w of its source column fixed so that the wall emits
+// from each column exactly the mass that left the fluid towards it from
+// that column in the same propagate (Ansumali and Karlin's diffuse
+// reflection, written for a lattice whose hops reach three rows).
+//
+// Wall table (FP64, per wall, WALL_TAB values), made once by k_wall_setup:
+//   [0, Q)    A_p = f_eq_p(1, 0, T_w)
+//   [Q, 2Q)   B_p = A_p - w_p, from the shifted equilibrium (no cancellation)
+//   [2Q]      K  = sum over the populations leaving the wall of |c_y| A_p
+//   [2Q + 1]  D  = the same sum of |c_y| B_p (K minus its value at T_w = 1)
+//   [2Q + 2]  K and [2Q + 3] D again, from A_p and B_p rounded to FP32: the
+//             shifted kernels emit with FP32 A_p, B_p, and with these sums
+//             the emitted mass equals the outgoing mass up to FP32
+//             arithmetic rounding, with no bias from the rounded constants.
+constexpr int WALL_TAB = 2 * Q + 4;
+
+template <typename C>
+struct BcArgs {
+    Force<C> force;
+    int walls;            // 0: periodic in y; 1: the two walls
+    const double* tab;    // [2][WALL_TAB]
+    const C* rho_w;       // [2][LX]: rho_w (FP64 storage) or rho_w - 1 (shifted), per column
+};
+
+__global__ void k_wall_setup(double* __restrict__ tab, double t_bottom, double t_top)
+{
+    const int wall = threadIdx.x;
+    if (wall >= 2) return;
+    double* t = tab + wall * WALL_TAB;
+    const double T = wall == 0 ? t_bottom : t_top;
+    equilibrium_f64<false>(1.0, 0.0, 0.0, T, [&](int p, double v) { t[p] = v; });
+    equilibrium_f64<true>(1.0, 0.0, 0.0, T, [&](int p, double v) { t[Q + p] = v; });
+    double k = 0.0, d = 0.0, k32 = 0.0, d32 = 0.0;
+    for (int p = 0; p < Q; ++p) {
+        const int cy = CY[p];
+        if (wall == 0 ? cy > 0 : cy < 0) {
+            const double n = (double)(cy > 0 ? cy : -cy);
+            k += n * t[p];
+            d += n * t[Q + p];
+            k32 += n * (double)(float)t[p];
+            d32 += n * (double)(float)t[Q + p];
+        }
+    }
+    t[2 * Q] = k;
+    t[2 * Q + 1] = d;
+    t[2 * Q + 2] = k32;
+    t[2 * Q + 3] = d32;
+}
+
+// Wall densities from the state before propagation: thread t < LX handles
+// column t of the bottom wall, LX <= t < 2 LX column t - LX of the top one.
+template <class P, class L>
+__global__ __launch_bounds__(BLOCK) void k_wall(const typename P::T* __restrict__ src, Geo g,
+                                                const double* __restrict__ tab, typename P::C* __restrict__ rho_w)
+{
+    using C = typename P::C;
+    constexpr int VL = vl_of<P>();
+    const int64_t t = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
+    if (t >= 2 * (int64_t)g.lx) return;
+    const int wall = t < g.lx ? 0 : 1;
+    const int x = (int)(t - (int64_t)wall * g.lx);
+    C sum = C(0);
+#pragma unroll
+    for (int p = 0; p < Q; ++p) {
+        const int cy = CY[p];
+        if (cy == 0 || (wall == 0) != (cy < 0)) continue;
+        const int n = cy > 0 ? cy : -cy;
+        for (int j = 0; j < n; ++j) {
+            const int y = wall == 0 ? j : g.ly - 1 - j;
+            if (y < 0 || y >= g.ly) continue;
+            sum += P::template load<false>(site_ptr<L, VL>(src, x, y, p, g), p);
+        }
+    }
+    const double* w = tab + wall * WALL_TAB;
+    C r;
+    if constexpr (P::shifted) r = (sum - (C)w[2 * Q + 3]) / (C)w[2 * Q + 2];
+    else r = sum / (C)w[2 * Q];
+    rho_w[t] = r;
+}
+
+// Replace, at a lane near a wall, the pulled values whose source row lies
+// beyond it by the wall's emission (rounded as storage would round it, so
+// that the fused step equals propagate + collide bit for bit).
+template <class P>
+__device__ inline void wall_emit(typename P::C (&v)[Q], int x, int y, const Geo& g,
+                                 const BcArgs<typename P::C>& bc)
+{
+    using C = typename P::C;
+    if (y >= 3 && y < g.ly - 3) return;
+#pragma unroll
+    for (int p = 0; p < Q; ++p) {
+        if (CY[p] == 0) continue;
+        const int sy = y - CY[p];
+        if (sy >= 0 && sy < g.ly) continue;
+        const int wall = sy < 0 ? 0 : 1;
+        const int sx = wrap_periodic(x - CX[p], g.lx);
+        const double* t = bc.tab + wall * WALL_TAB;
+        const C rw = bc.rho_w[(int64_t)wall * g.lx + sx];
+        C e;
+        if constexpr (P::shifted) e = fma_(rw, (C)t[p], (C)t[Q + p]);
+        else e = rw * t[p];
+        v[p] = value_of<P>(word_of<P>(e, p), p);
+    }
+}
+
 // ---- kernels ---------------------------------------------------------------
 // Every lattice kernel is launched row-tiled: LX * tpr workgroups of BLOCK
 // lanes (see row_tile_site).
@@ -129,12 +239,15 @@ __global__ __launch_bounds__(BLOCK) void k_init(typename P::T* __restrict__ dst,
                                 [&](int p, double v) { store_from_f64<P>(st.own(dst, p, g), p, v); });
 }
 
-// Pure gather, bit copy of every population from its upstream site.
-template <class P, class L>
+// Pure gather, bit copy of every population from its upstream site; with
+// WALLS, the values emitted by the walls replace those from beyond them.
+template <class P, class L, bool WALLS>
 __global__ __launch_bounds__(BLOCK) void k_propagate(const typename P::Word* __restrict__ src,
-                                                     typename P::Word* __restrict__ dst, Geo g)
+                                                     typename P::Word* __restrict__ dst, Geo g,
+                                                     BcArgs<typename P::C> bc)
 {
     using W = typename P::Word;
+    using C = typename P::C;
     constexpr int VL = vl_of<P>();
     int xrow, r;
     int64_t tile;
@@ -144,14 +257,25 @@ __global__ __launch_bounds__(BLOCK) void k_propagate(const typename P::Word* __r
     W w[Q];
 #pragma unroll
     for (int p = 0; p < Q; ++p) w[p] = ld_stream<W, L::stream_loads>(st.src(src, p, g));
+    if constexpr (WALLS) {
+        if (st.y < 3 || st.y >= g.ly - 3) {
+            C v[Q];
+#pragma unroll
+            for (int p = 0; p < Q; ++p) v[p] = value_of<P>(w[p], p);
+            wall_emit<P>(v, st.x, st.y, g, bc);
+#pragma unroll
+            for (int p = 0; p < Q; ++p) w[p] = word_of<P>(v[p], p);
+        }
+    }
     // 2-byte words are stored without the streaming hint (see PrecF16S::store)
 #pragma unroll
     for (int p = 0; p < Q; ++p) st_stream<W, L::stream_stores && (sizeof(W) > 2)>(st.own(dst, p, g), w[p]);
 }
 
-// Collide in place on the current buffer.
-template <class P, class L, bool COMP>
-__global__ __launch_bounds__(BLOCK) void k_collide(typename P::T* __restrict__ buf, Geo g, double omega)
+// Collide in place on the current buffer (with the body force if BC).
+template <class P, class L, bool COMP, bool BC>
+__global__ __launch_bounds__(BLOCK) void k_collide(typename P::T* __restrict__ buf, Geo g, double omega,
+                                                   BcArgs<typename P::C> bc)
 {
     using C = typename P::C;
     D2Q37_SITE(P, L);
@@ -159,16 +283,19 @@ __global__ __launch_bounds__(BLOCK) void k_collide(typename P::T* __restrict__ b
     C v[Q];
 #pragma unroll
     for (int p = 0; p < Q; ++p) v[p] = P::template load<L::stream_loads>(st.own(buf, p, g), p);
-    collide_site<P, COMP>(v, (C)omega, [&](int p, C res) { P::template store<L::stream_stores>(st.own(buf, p, g), p, res); });
+    collide_site_f<P, COMP, BC>(v, (C)omega, bc.force,
+                                [&](int p, C res) { P::template store<L::stream_stores>(st.own(buf, p, g), p, res); });
 }
 
 // Fused step src -> dst: pull the 37 populations, collide, store at the own
 // site. With AUDIT, the FP64 mass/momentum/energy of the stored result are
-// reduced per workgroup into partials[4 * tile].
-template <class P, class L, bool COMP, bool AUDIT>
+// reduced per workgroup into partials[4 * tile]. With BC, the walls (if
+// bc.walls) replace the values pulled from beyond them, and the collide
+// applies the body force (zero force rounds exactly as without BC).
+template <class P, class L, bool COMP, bool AUDIT, bool BC>
 __global__ __launch_bounds__(BLOCK) void k_step(const typename P::T* __restrict__ src,
                                                 typename P::T* __restrict__ dst, Geo g, double omega,
-                                                double* __restrict__ partials)
+                                                double* __restrict__ partials, BcArgs<typename P::C> bc)
 {
     using C = typename P::C;
     D2Q37_SITE(P, L);
@@ -177,15 +304,20 @@ __global__ __launch_bounds__(BLOCK) void k_step(const typename P::T* __restrict_
         C v[Q];
 #pragma unroll
         for (int p = 0; p < Q; ++p) v[p] = P::template load<L::stream_loads>(st.src(src, p, g), p);
+        if constexpr (BC) {
+            if (bc.walls) wall_emit<P>(v, st.x, st.y, g, bc);
+        }
         if constexpr (AUDIT) {
             double d[Q];
-            collide_site<P, COMP>(v, (C)omega, [&](int p, C res) {
+            collide_site_f<P, COMP, BC>(v, (C)omega, bc.force, [&](int p, C res) {
                 P::template store<L::stream_stores>(st.own(dst, p, g), p, res);
                 d[p] = stored_as_f64<P>(res, p);
             });
             audit_site(d, acc);
         } else {
-            collide_site<P, COMP>(v, (C)omega, [&](int p, C res) { P::template store<L::stream_stores>(st.own(dst, p, g), p, res); });
+            collide_site_f<P, COMP, BC>(v, (C)omega, bc.force, [&](int p, C res) {
+                P::template store<L::stream_stores>(st.own(dst, p, g), p, res);
+            });
         }
     } else if (!AUDIT) {
         return;

@@ -34,6 +34,10 @@ struct lb_ctx {
     int lgrid;             // their persistent grid: min(tiles, compute units)
     int64_t audit_parts;   // partial sums written by the last fused audit
     bool fused_audit_valid;
+    bool bc;               // walls or a nonzero body force: the kernels' BC path
+    double force[3];       // R tau gx, R tau gy, tau (1 - tau) |g|^2 / 2
+    double* wall_tab;      // scratch: [2][WALL_TAB] (walls only)
+    double* rho_w;         // scratch: [2][lx] wall densities (FP32 for shifted storage)
     int device;            // device current at lb_init (where the buffers live)
     void* static_scratch;  // that device's address of `scratch` (lb_audit_static), or NULL
     char err[512];
@@ -128,6 +132,32 @@ void* other_buf(lb_ctx* c) { return c->cfg.buf[c->cur ^ 1]; }
 int launch_status(lb_ctx* c, const char* what) { return check_hip(c, hipGetLastError(), what); }
 
 dim3 grid_of(const lb_ctx* c) { return dim3((unsigned)c->nblocks); }
+
+template <typename C>
+BcArgs<C> bc_args(const lb_ctx* c)
+{
+    BcArgs<C> b;
+    b.force.dUx = (C)c->force[0];
+    b.force.dUy = (C)c->force[1];
+    b.force.dt = (C)c->force[2];
+    b.walls = c->cfg.walls;
+    b.tab = c->wall_tab;
+    b.rho_w = (const C*)c->rho_w;
+    return b;
+}
+
+// Wall densities of the current buffer (before a propagate), walls only.
+void launch_wall(lb_ctx* c)
+{
+    with_config(c->cfg, [&](auto p, auto l) {
+        using P = decltype(p);
+        using L = decltype(l);
+        const int64_t threads = 2 * (int64_t)c->geo.lx;
+        hipLaunchKernelGGL((k_wall<P, L>), dim3((unsigned)div_up(threads, BLOCK)), dim3(BLOCK), 0, c->stream,
+                           (const typename P::T*)cur_buf(c), c->geo, (const double*)c->wall_tab,
+                           (typename P::C*)c->rho_w);
+    });
+}
 dim3 lgrid_of(const lb_ctx* c) { return dim3((unsigned)c->lgrid); }
 
 constexpr int MAX_DEVICES = 64;
@@ -216,9 +246,11 @@ size_t lb_scratch_bytes(int32_t lx, int32_t ly)
     if (lx < 1 || ly < 1) return 0;
     const int64_t n = (int64_t)lx * ly;
     if (n >= ((int64_t)1 << 31)) return 0;
-    // one partial sum of 4 doubles per row-tiled workgroup, the 4 totals and
-    // two 64-bit counters of the learned collide
-    return round256((size_t)((int64_t)lx * div_up(ly, BLOCK) * 4 + 4 + 2) * sizeof(double));
+    // one partial sum of 4 doubles per row-tiled workgroup, the 4 totals, two
+    // 64-bit counters of the learned collide, the walls' table and their
+    // per-column densities
+    return round256((size_t)((int64_t)lx * div_up(ly, BLOCK) * 4 + 4 + 2 + 2 * WALL_TAB + 2 * (int64_t)lx) *
+                    sizeof(double));
 }
 
 int lb_init(lb_ctx** out, const lb_config* cfg, const double* rho, const double* ux, const double* uy,
@@ -252,6 +284,12 @@ int lb_init(lb_ctx** out, const lb_config* cfg, const double* rho, const double*
         return fail(nullptr, LB_EINVAL, "lb_init: scratch_bytes %zu < %zu", k.scratch_bytes,
                     lb_scratch_bytes(k.lx, k.ly));
     if (!rho || !ux || !uy || !T) return fail(nullptr, LB_EINVAL, "lb_init: a field pointer is NULL");
+    if (!std::isfinite(k.gx) || !std::isfinite(k.gy) || std::fabs(k.gx) > 1.0 || std::fabs(k.gy) > 1.0)
+        return fail(nullptr, LB_EINVAL, "lb_init: force (%g, %g) must be finite with |g| <= 1", k.gx, k.gy);
+    if (k.walls != 0 && k.walls != 1) return fail(nullptr, LB_EINVAL, "lb_init: walls = %d must be 0 or 1", k.walls);
+    if (k.walls && (!(k.t_bottom > 0.0) || !(k.t_top > 0.0) || !std::isfinite(k.t_bottom) || !std::isfinite(k.t_top)))
+        return fail(nullptr, LB_EINVAL, "lb_init: wall temperatures (%g, %g) must be finite and > 0", k.t_bottom,
+                    k.t_top);
 
     lb_ctx* c = new (std::nothrow) lb_ctx();
     if (!c) return fail(nullptr, LB_EINVAL, "lb_init: out of host memory");
@@ -269,6 +307,12 @@ int lb_init(lb_ctx** out, const lb_config* cfg, const double* rho, const double*
     c->partials = (double*)k.scratch;
     c->totals = c->partials + 4 * c->nblocks;
     c->counts = (unsigned long long*)(c->totals + 4);
+    c->wall_tab = c->totals + 4 + 2;
+    c->rho_w = c->wall_tab + 2 * WALL_TAB;
+    c->bc = k.walls != 0 || k.gx != 0.0 || k.gy != 0.0;
+    c->force[0] = R * k.tau * k.gx;
+    c->force[1] = R * k.tau * k.gy;
+    c->force[2] = k.tau * (1.0 - k.tau) * (k.gx * k.gx + k.gy * k.gy) / 2.0;
     c->mlp = nullptr;
     c->threshold = 0.0f;
     c->lgeo = c->geo;
@@ -289,6 +333,7 @@ int lb_init(lb_ctx** out, const lb_config* cfg, const double* rho, const double*
         hipLaunchKernelGGL((k_init<P, L>), grid_of(c), dim3(BLOCK), 0, c->stream, (typename P::T*)k.buf[0],
                            c->geo, rho, ux, uy, T);
     });
+    if (k.walls) hipLaunchKernelGGL(k_wall_setup, dim3(1), dim3(64), 0, c->stream, c->wall_tab, k.t_bottom, k.t_top);
     if (hipMemsetAsync(c->counts, 0, 2 * sizeof(unsigned long long), c->stream) != hipSuccess) {
         snprintf(g_err, sizeof g_err, "lb_init: clearing the counters failed");
         delete c;
@@ -307,11 +352,17 @@ int lb_init(lb_ctx** out, const lb_config* cfg, const double* rho, const double*
 int lb_propagate(lb_ctx* c)
 {
     if (!c) return fail(nullptr, LB_EINVAL, "lb_propagate: ctx is NULL");
+    if (c->cfg.walls) launch_wall(c);
     with_config(c->cfg, [&](auto p, auto l) {
         using P = decltype(p);
         using L = decltype(l);
-        hipLaunchKernelGGL((k_propagate<P, L>), grid_of(c), dim3(BLOCK), 0, c->stream,
-                           (const typename P::Word*)cur_buf(c), (typename P::Word*)other_buf(c), c->geo);
+        const auto bc = bc_args<typename P::C>(c);
+        if (c->cfg.walls)
+            hipLaunchKernelGGL((k_propagate<P, L, true>), grid_of(c), dim3(BLOCK), 0, c->stream,
+                               (const typename P::Word*)cur_buf(c), (typename P::Word*)other_buf(c), c->geo, bc);
+        else
+            hipLaunchKernelGGL((k_propagate<P, L, false>), grid_of(c), dim3(BLOCK), 0, c->stream,
+                               (const typename P::Word*)cur_buf(c), (typename P::Word*)other_buf(c), c->geo, bc);
     });
     const int rc = launch_status(c, "lb_propagate");
     if (rc != LB_OK) return rc;
@@ -340,12 +391,16 @@ int lb_collide(lb_ctx* c)
         with_config(c->cfg, [&](auto p, auto l) {
             using P = decltype(p);
             using L = decltype(l);
-            if (comp)
-                hipLaunchKernelGGL((k_collide<P, L, true>), grid_of(c), dim3(BLOCK), 0, c->stream,
-                                   (typename P::T*)cur_buf(c), c->geo, omega);
-            else
-                hipLaunchKernelGGL((k_collide<P, L, false>), grid_of(c), dim3(BLOCK), 0, c->stream,
-                                   (typename P::T*)cur_buf(c), c->geo, omega);
+            const auto bc = bc_args<typename P::C>(c);
+            auto* buf = (typename P::T*)cur_buf(c);
+#define D2Q37_COLL(CMP, BCF) \
+    hipLaunchKernelGGL((k_collide<P, L, CMP, BCF>), grid_of(c), dim3(BLOCK), 0, c->stream, buf, c->geo, omega, bc)
+            if (comp) {
+                if (c->bc) D2Q37_COLL(true, true); else D2Q37_COLL(true, false);
+            } else {
+                if (c->bc) D2Q37_COLL(false, true); else D2Q37_COLL(false, false);
+            }
+#undef D2Q37_COLL
         });
     }
     const int rc = launch_status(c, "lb_collide");
@@ -390,19 +445,24 @@ int lb_step(lb_ctx* c, int32_t nsteps)
             if (audit) c->audit_parts = c->lgrid;
             continue;
         }
+        if (c->cfg.walls) launch_wall(c);
         with_config(c->cfg, [&](auto p, auto l) {
             using P = decltype(p);
             using L = decltype(l);
             const auto* src = (const typename P::T*)cur_buf(c);
             auto* dst = (typename P::T*)other_buf(c);
-#define D2Q37_STEP(CMP, AUD)                                                                              \
-    hipLaunchKernelGGL((k_step<P, L, CMP, AUD>), grid_of(c), dim3(BLOCK), 0, c->stream, src, dst, c->geo, omega, \
-                       c->partials)
+            const auto bc = bc_args<typename P::C>(c);
+#define D2Q37_STEP(CMP, AUD, BCF)                                                                              \
+    hipLaunchKernelGGL((k_step<P, L, CMP, AUD, BCF>), grid_of(c), dim3(BLOCK), 0, c->stream, src, dst, c->geo, omega, \
+                       c->partials, bc)
+#define D2Q37_STEP_BC(CMP, AUD) \
+    do { if (c->bc) D2Q37_STEP(CMP, AUD, true); else D2Q37_STEP(CMP, AUD, false); } while (0)
             if (comp) {
-                if (audit) D2Q37_STEP(true, true); else D2Q37_STEP(true, false);
+                if (audit) D2Q37_STEP_BC(true, true); else D2Q37_STEP_BC(true, false);
             } else {
-                if (audit) D2Q37_STEP(false, true); else D2Q37_STEP(false, false);
+                if (audit) D2Q37_STEP_BC(false, true); else D2Q37_STEP_BC(false, false);
             }
+#undef D2Q37_STEP_BC
 #undef D2Q37_STEP
         });
         const int rc = launch_status(c, "lb_step");
@@ -490,6 +550,8 @@ int lb_set_surrogate(lb_ctx* c, const lb_mlp* m, double threshold)
     }
     if (c->cfg.precision != LB_FP32_SHIFTED)
         return fail(c, LB_EUNSUPPORTED, "lb_set_surrogate: the learned collide needs FP32-shifted populations");
+    if (c->bc)
+        return fail(c, LB_EUNSUPPORTED, "lb_set_surrogate: the learned collide runs on periodic lattices without force");
     if (!(threshold >= 0.0) || !std::isfinite(threshold))
         return fail(c, LB_EINVAL, "lb_set_surrogate: threshold %g must be finite and >= 0", threshold);
     if ((int64_t)c->geo.lx * c->geo.ly > (int64_t)UINT32_MAX)

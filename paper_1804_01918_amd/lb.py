@@ -50,6 +50,11 @@ class Config(ctypes.Structure):
         ("scratch", ctypes.c_void_p),
         ("scratch_bytes", ctypes.c_size_t),
         ("stream", ctypes.c_void_p),
+        ("gx", ctypes.c_double),
+        ("gy", ctypes.c_double),
+        ("walls", ctypes.c_int32),
+        ("t_bottom", ctypes.c_double),
+        ("t_top", ctypes.c_double),
     ]
 
 
@@ -335,10 +340,13 @@ class Lattice:
 
     def __init__(self, lx: int, ly: int, tau: float, fields, precision: str = "f64",
                  layout: str = "soa", compensated: bool | None = None, audit: bool = False,
-                 device: str = "cuda"):
+                 device: str = "cuda", force=(0.0, 0.0), walls: bool = False, t_bottom: float = 1.0,
+                 t_top: float = 1.0):
         """compensated=None picks the default of the precision: compensated
         FP32 moment sums for f32s; plain sums for f16s, whose 11-bit storage
-        rounding is far above the FP32 summation error."""
+        rounding is far above the FP32 summation error. force: body force
+        (acceleration per step, thermal units); walls: diffuse walls at rest
+        below row 0 (t_bottom) and above row ly - 1 (t_top)."""
         torch = _torch()
         if compensated is None:
             compensated = precision == "f32s"
@@ -360,6 +368,10 @@ class Lattice:
         self.cfg.buf[0], self.cfg.buf[1] = self.bufs[0].data_ptr(), self.bufs[1].data_ptr()
         self.cfg.scratch, self.cfg.scratch_bytes = self.scratch.data_ptr(), sbytes
         self.cfg.stream = self.stream.cuda_stream
+        self.force = (float(force[0]), float(force[1]))
+        self.cfg.gx, self.cfg.gy = self.force
+        self.cfg.walls = int(bool(walls))
+        self.cfg.t_bottom, self.cfg.t_top = float(t_bottom), float(t_top)
         fl = [self._field(a) for a in fields]
         self._ctx = None
         self._ctx = lb_init(self.cfg, *fl)

@@ -107,6 +107,9 @@ def _cfg(**kw):
     c.scratch = kw.get("scratch", 0x30000)
     c.scratch_bytes = kw.get("scratch_bytes", 1 << 20)
     c.stream = None
+    c.gx, c.gy = kw.get("gx", 0.0), kw.get("gy", 0.0)
+    c.walls = kw.get("walls", 0)
+    c.t_bottom, c.t_top = kw.get("t_bottom", 1.0), kw.get("t_top", 1.0)
     return c
 
 
@@ -125,6 +128,12 @@ def _cfg(**kw):
     (dict(b1=0x10000), lb.LB_EINVAL),
     (dict(scratch=0), lb.LB_EINVAL),
     (dict(scratch_bytes=8), lb.LB_EINVAL),
+    (dict(gx=float("nan")), lb.LB_EINVAL),
+    (dict(gy=1.5), lb.LB_EINVAL),
+    (dict(walls=2), lb.LB_EINVAL),
+    (dict(walls=1, t_bottom=0.0), lb.LB_EINVAL),
+    (dict(walls=1, t_top=float("inf")), lb.LB_EINVAL),
+    (dict(walls=1, t_top=-1.0), lb.LB_EINVAL),
 ])
 def test_init_rejects_before_device_work(kw, code):
     """Every invalid configuration is refused by validation, before any HIP
