@@ -322,6 +322,48 @@ def energy_variant(args, torch, lb, fields, net):
     return out
 
 
+# Rayleigh-Taylor setting with gravity and walls: acceleration along -y
+# (thermal units per step) and the walls at the two layers' temperatures.
+RT_GRAVITY = (0.0, -1e-4)
+RT_WALLS = dict(walls=True, t_bottom=1.05, t_top=0.95)
+
+
+def gravity_walls_variant(args, torch, lb, inputs):
+    """2048 x 2048 Rayleigh-Taylor-like state under gravity between diffuse
+    walls (the paper's production setting), CAoSoA fused step in each
+    precision: MLUPS, the FP64 mass audit over the run, and the shifted
+    forms' field errors against the FP64 run after ERR_STEPS_2048 steps."""
+    from paper_1804_01918_amd.roofline import HBM_PEAK_GBS, bytes_per_site
+    fields = [torch.from_numpy(a).cuda() for a in inputs.rayleigh_taylor(LX, LY, seed=0)]
+    timed = ERR_STEPS_2048 - args.warmup
+    out = {"lattice": [LX, LY], "gravity": list(RT_GRAVITY), **RT_WALLS, "steps": ERR_STEPS_2048,
+           "timed_steps": timed}
+    ref = None
+    for prec in ("f64", "f32s", "f16s"):
+        lat = lb.Lattice(LX, LY, TAU, fields, precision=prec, layout="caosoa", audit=True, force=RT_GRAVITY,
+                         **RT_WALLS)
+        a0 = lat.audit()
+        lat.step(args.warmup)
+        dt = timed_steps(lat, torch, timed)
+        a1 = lat.audit()
+        mom = lat.moments()
+        lat.close()
+        del lat
+        m = LX * LY * timed / dt / 1e6
+        r = {"mlups": m, "hbm_frac": m * 1e6 * bytes_per_site(prec[:3]) / (HBM_PEAK_GBS * 1e9),
+             "mass_drift_rel": float((a1[0] - a0[0]) / a0[0])}
+        if prec == "f64":
+            ref = mom
+        else:
+            r["field_error_vs_f64"] = field_errors(ref, mom)
+            del mom
+        out[prec] = r
+        torch.cuda.empty_cache()
+    del ref, fields
+    torch.cuda.empty_cache()
+    return out
+
+
 def scale_variant(args, torch, inputs, run, counts, net):
     """8192 x 8192 Rayleigh-Taylor-like lattice: FP64, FP32-shifted and the
     learned collide on the same GPU, errors against the FP64 run."""
@@ -364,7 +406,8 @@ def main():
     ap.add_argument("--no-energy", action="store_true")
     ap.add_argument("--scale-steps", type=int, default=ERR_STEPS_8192,
                     help="total steps (warm-up included) of the 8192 x 8192 runs")
-    ap.add_argument("--only", default=None, help="precision:layout[:split], or 'learned', to time alone")
+    ap.add_argument("--only", default=None,
+                    help="precision:layout[:split][:walls], or 'learned', to time alone")
     ap.add_argument("--copy-bytes", type=int, default=0,
                     help="only run the library's copy kernel on buffers of this size (counter calibration)")
     ap.add_argument("--copy-reps", type=int, default=5)
@@ -388,9 +431,10 @@ def main():
     counts = {}
 
     def run(prec, layout, steps, warmup, split=False, keep=False, state=None, net=None, threshold=THRESHOLD,
-            compensated=None):
+            compensated=None, bc=None):
         lx, ly, flds = state if state is not None else (LX, LY, fields)
-        lat = lb.Lattice(lx, ly, TAU, flds, precision=prec, layout=layout, audit=True, compensated=compensated)
+        lat = lb.Lattice(lx, ly, TAU, flds, precision=prec, layout=layout, audit=True, compensated=compensated,
+                         **(bc or {}))
         if net is not None:
             lat.set_surrogate(net, threshold)
         if split:
@@ -418,8 +462,13 @@ def main():
         net.close()
         return
     if args.only:
+        # precision:layout[:split][:walls]; "walls" runs the Rayleigh-Taylor-like
+        # state under gravity between the diffuse walls
         parts = args.only.split(":")
-        dt, _ = run(parts[0], parts[1], args.steps, args.warmup, split=len(parts) > 2)
+        walls = "walls" in parts[2:]
+        state = (LX, LY, [torch.from_numpy(a).cuda() for a in inputs.rayleigh_taylor(LX, LY, seed=0)]) if walls else None
+        dt, _ = run(parts[0], parts[1], args.steps, args.warmup, split="split" in parts[2:], state=state,
+                    bc=dict(force=RT_GRAVITY, **RT_WALLS) if walls else None)
         print(json.dumps({"only": args.only, "mlups": nsites * args.steps / dt / 1e6,
                           "ms_per_step": dt / args.steps * 1e3}))
         return
@@ -512,6 +561,7 @@ def main():
             variants["rayleigh_taylor_2048"][f"{prec}_field_error_vs_f64"] = field_errors(rt_ref, mom)
         _, mom = run("f32s", "caosoa", err_timed, args.warmup, keep=True, state=rt, compensated=False)
         variants["rayleigh_taylor_2048"]["f32s_uncompensated_field_error_vs_f64"] = field_errors(rt_ref, mom)
+        variants["rayleigh_taylor_gravity_walls_2048"] = gravity_walls_variant(args, torch, lb, inputs)
         out["variants"] = variants
 
     if not args.no_learned:

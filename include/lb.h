@@ -143,7 +143,12 @@ int lb_init(lb_ctx **out, const lb_config *cfg, const double *rho, const double 
  * replaced by the one at s - c_p (pull gather, periodic), copied bit for bit
  * into the other buffer, which then becomes current. With walls, the
  * populations pulled from beyond a wall are the wall's emission (see
- * lb_config.walls), computed from the current buffer before the gather. */
+ * lb_config.walls): before the gather, each wall's densities are summed
+ * from the slots of the current buffer that leave through it, and those
+ * slots, which the propagate would otherwise only move across the lattice
+ * to the opposite wall, receive the other wall's emission; so with walls
+ * the buffer that stops being current differs from the state it held in
+ * those slots only. */
 int lb_propagate(lb_ctx *ctx);
 
 /* Collide (paper, Section 3): per site, moments, equilibrium and BGK

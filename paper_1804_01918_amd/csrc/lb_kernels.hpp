@@ -102,7 +102,7 @@ __device__ inline void block_reduce4(double (&acc)[4], double* out)
     }
 }
 
-// ---- walls and body force -------------------------------------------------
+// ---- walls ------------------------------------------------------------------
 // Diffuse walls at rest on the planes y = -1/2 (wall 0, bottom) and
 // y = LY - 1/2 (wall 1, top), each at its own temperature; x stays periodic.
 // In the pull propagate a population whose source row lies beyond a wall is
@@ -111,6 +111,16 @@ __device__ inline void block_reduce4(double (&acc)[4], double* out)
 // from each column exactly the mass that left the fluid towards it from
 // that column in the same propagate (Ansumali and Karlin's diffuse
 // reflection, written for a lattice whose hops reach three rows).
+//
+// No extra rows are stored: a periodic pull that crosses a wall reads a
+// slot holding a population that leaves through the opposite wall (for
+// c_y > 0 the rows LY - c_y .. LY - 1, for c_y < 0 the rows 0 .. -c_y - 1),
+// and that slot has no other reader. k_wall therefore, per column x, sums
+// those leaving values into the two wall densities and then overwrites each
+// of them with the emission its one reader needs: the bottom wall's for the
+// slots that leave through the top, and the other way round. The unchanged
+// periodic kernels then pull the walls' emission. (The current buffer is
+// changed only in these dead slots, just before it is propagated.)
 //
 // Wall table (FP64, per wall, WALL_TAB values), made once by k_wall_setup:
 //   [0, Q)    A_p = f_eq_p(1, 0, T_w)
@@ -122,14 +132,6 @@ __device__ inline void block_reduce4(double (&acc)[4], double* out)
 //             the emitted mass equals the outgoing mass up to FP32
 //             arithmetic rounding, with no bias from the rounded constants.
 constexpr int WALL_TAB = 2 * Q + 4;
-
-template <typename C>
-struct BcArgs {
-    Force<C> force;
-    int walls;            // 0: periodic in y; 1: the two walls
-    const double* tab;    // [2][WALL_TAB]
-    const C* rho_w;       // [2][LX]: rho_w (FP64 storage) or rho_w - 1 (shifted), per column
-};
 
 __global__ void k_wall_setup(double* __restrict__ tab, double t_bottom, double t_top)
 {
@@ -156,59 +158,93 @@ __global__ void k_wall_setup(double* __restrict__ tab, double t_bottom, double t
     t[2 * Q + 3] = d32;
 }
 
-// Wall densities from the state before propagation: thread t < LX handles
-// column t of the bottom wall, LX <= t < 2 LX column t - LX of the top one.
+// The slots that leave the fluid towards a wall in one propagate: for the
+// bottom wall the populations with c_y < 0 in rows j < -c_y, for the top one
+// those with c_y > 0 in rows LY - 1 - j, j < c_y; 26 per wall and column,
+// listed as (p, j) with the FP16 storage scale of p and its inverse.
+struct WallPairs {
+    int8_t p[2][32];
+    int8_t j[2][32];
+    float s16[2][32];
+    float inv_s16[2][32];
+};
+constexpr WallPairs make_wall_pairs()
+{
+    WallPairs w{};
+    for (int wall = 0; wall < 2; ++wall) {
+        int k = 0;
+        for (int p = 0; p < Q; ++p) {
+            const int cy = CY[p];
+            if (cy == 0 || (wall == 0) != (cy < 0)) continue;
+            const int n = cy > 0 ? cy : -cy;
+            for (int j = 0; j < n; ++j) {
+                w.p[wall][k] = (int8_t)p;
+                w.j[wall][k] = (int8_t)j;
+                w.s16[wall][k] = S16[shell_of_c2(c2_of(p))];
+                w.inv_s16[wall][k] = 1.0f / S16[shell_of_c2(c2_of(p))];
+                ++k;
+            }
+        }
+        for (; k < 32; ++k) {
+            w.p[wall][k] = -1;
+            w.j[wall][k] = 0;
+            w.s16[wall][k] = 0.0f;
+            w.inv_s16[wall][k] = 0.0f;
+        }
+    }
+    return w;
+}
+static __constant__ WallPairs WALL_PAIRS = make_wall_pairs();
+
+// One wavefront per column x of the current buffer: lanes 0..25 hold the
+// slots leaving towards the bottom wall, lanes 32..57 those leaving towards
+// the top one. Each half is summed in a fixed butterfly order into its
+// wall's density; then every slot receives the other wall's emission for
+// its population (see the comment above).
 template <class P, class L>
-__global__ __launch_bounds__(BLOCK) void k_wall(const typename P::T* __restrict__ src, Geo g,
-                                                const double* __restrict__ tab, typename P::C* __restrict__ rho_w)
+__global__ __launch_bounds__(BLOCK) void k_wall(typename P::T* __restrict__ buf, Geo g,
+                                                const double* __restrict__ tab)
 {
     using C = typename P::C;
     constexpr int VL = vl_of<P>();
-    const int64_t t = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
-    if (t >= 2 * (int64_t)g.lx) return;
-    const int wall = t < g.lx ? 0 : 1;
-    const int x = (int)(t - (int64_t)wall * g.lx);
-    C sum = C(0);
-#pragma unroll
-    for (int p = 0; p < Q; ++p) {
-        const int cy = CY[p];
-        if (cy == 0 || (wall == 0) != (cy < 0)) continue;
-        const int n = cy > 0 ? cy : -cy;
-        for (int j = 0; j < n; ++j) {
-            const int y = wall == 0 ? j : g.ly - 1 - j;
-            if (y < 0 || y >= g.ly) continue;
-            sum += P::template load<false>(site_ptr<L, VL>(src, x, y, p, g), p);
+    const int lane = threadIdx.x & 63;
+    const int64_t col = (int64_t)blockIdx.x * (BLOCK / 64) + (threadIdx.x >> 6);
+    if (col >= g.lx) return;  // whole wavefronts
+    const int x = (int)col;
+    const int wall = lane >> 5, k = lane & 31;
+    const int p = WALL_PAIRS.p[wall][k];
+    typename P::T* a = nullptr;
+    C v = C(0);
+    if (p >= 0) {
+        const int j = WALL_PAIRS.j[wall][k];
+        const int y = wall == 0 ? j : g.ly - 1 - j;
+        if (y >= 0 && y < g.ly) {
+            a = const_cast<typename P::T*>(site_ptr<L, VL>((const typename P::T*)buf, x, y, p, g));
+            if constexpr (P::kind == PREC_F16S)
+                v = __half2float(__ushort_as_half(*a)) * WALL_PAIRS.inv_s16[wall][k];
+            else
+                v = *a;
         }
     }
-    const double* w = tab + wall * WALL_TAB;
-    C r;
-    if constexpr (P::shifted) r = (sum - (C)w[2 * Q + 3]) / (C)w[2 * Q + 2];
-    else r = sum / (C)w[2 * Q];
-    rho_w[t] = r;
-}
-
-// Replace, at a lane near a wall, the pulled values whose source row lies
-// beyond it by the wall's emission (rounded as storage would round it, so
-// that the fused step equals propagate + collide bit for bit).
-template <class P>
-__device__ inline void wall_emit(typename P::C (&v)[Q], int x, int y, const Geo& g,
-                                 const BcArgs<typename P::C>& bc)
-{
-    using C = typename P::C;
-    if (y >= 3 && y < g.ly - 3) return;
 #pragma unroll
-    for (int p = 0; p < Q; ++p) {
-        if (CY[p] == 0) continue;
-        const int sy = y - CY[p];
-        if (sy >= 0 && sy < g.ly) continue;
-        const int wall = sy < 0 ? 0 : 1;
-        const int sx = wrap_periodic(x - CX[p], g.lx);
-        const double* t = bc.tab + wall * WALL_TAB;
-        const C rw = bc.rho_w[(int64_t)wall * g.lx + sx];
+    for (int off = 16; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
+    // v: this half's outgoing mass; the other half's is 32 lanes away
+    const C other = __shfl_xor(v, 32, 64);
+    if (a) {
+        // the slot leaves through `wall`; its reader pulls through the other one
+        const int ew = 1 - wall;
+        const double* w = tab + ew * WALL_TAB;
         C e;
-        if constexpr (P::shifted) e = fma_(rw, (C)t[p], (C)t[Q + p]);
-        else e = rw * t[p];
-        v[p] = value_of<P>(word_of<P>(e, p), p);
+        if constexpr (P::shifted) {
+            const C rw1 = (other - (C)w[2 * Q + 3]) / (C)w[2 * Q + 2];  // rho_w - 1
+            e = fma_(rw1, (C)w[p], (C)w[Q + p]);
+        } else {
+            e = (other / (C)w[2 * Q]) * w[p];
+        }
+        if constexpr (P::kind == PREC_F16S)
+            *a = (uint16_t)__half_as_ushort(__float2half_rn(e * WALL_PAIRS.s16[wall][k]));
+        else
+            *a = e;
     }
 }
 
@@ -239,15 +275,12 @@ __global__ __launch_bounds__(BLOCK) void k_init(typename P::T* __restrict__ dst,
                                 [&](int p, double v) { store_from_f64<P>(st.own(dst, p, g), p, v); });
 }
 
-// Pure gather, bit copy of every population from its upstream site; with
-// WALLS, the values emitted by the walls replace those from beyond them.
-template <class P, class L, bool WALLS>
+// Pure gather, bit copy of every population from its upstream site.
+template <class P, class L>
 __global__ __launch_bounds__(BLOCK) void k_propagate(const typename P::Word* __restrict__ src,
-                                                     typename P::Word* __restrict__ dst, Geo g,
-                                                     BcArgs<typename P::C> bc)
+                                                     typename P::Word* __restrict__ dst, Geo g)
 {
     using W = typename P::Word;
-    using C = typename P::C;
     constexpr int VL = vl_of<P>();
     int xrow, r;
     int64_t tile;
@@ -257,25 +290,15 @@ __global__ __launch_bounds__(BLOCK) void k_propagate(const typename P::Word* __r
     W w[Q];
 #pragma unroll
     for (int p = 0; p < Q; ++p) w[p] = ld_stream<W, L::stream_loads>(st.src(src, p, g));
-    if constexpr (WALLS) {
-        if (st.y < 3 || st.y >= g.ly - 3) {
-            C v[Q];
-#pragma unroll
-            for (int p = 0; p < Q; ++p) v[p] = value_of<P>(w[p], p);
-            wall_emit<P>(v, st.x, st.y, g, bc);
-#pragma unroll
-            for (int p = 0; p < Q; ++p) w[p] = word_of<P>(v[p], p);
-        }
-    }
     // 2-byte words are stored without the streaming hint (see PrecF16S::store)
 #pragma unroll
     for (int p = 0; p < Q; ++p) st_stream<W, L::stream_stores && (sizeof(W) > 2)>(st.own(dst, p, g), w[p]);
 }
 
-// Collide in place on the current buffer (with the body force if BC).
-template <class P, class L, bool COMP, bool BC>
+// Collide in place on the current buffer (with the body force if FORCE).
+template <class P, class L, bool COMP, bool FORCE>
 __global__ __launch_bounds__(BLOCK) void k_collide(typename P::T* __restrict__ buf, Geo g, double omega,
-                                                   BcArgs<typename P::C> bc)
+                                                   Force<typename P::C> force)
 {
     using C = typename P::C;
     D2Q37_SITE(P, L);
@@ -283,19 +306,20 @@ __global__ __launch_bounds__(BLOCK) void k_collide(typename P::T* __restrict__ b
     C v[Q];
 #pragma unroll
     for (int p = 0; p < Q; ++p) v[p] = P::template load<L::stream_loads>(st.own(buf, p, g), p);
-    collide_site_f<P, COMP, BC>(v, (C)omega, bc.force,
-                                [&](int p, C res) { P::template store<L::stream_stores>(st.own(buf, p, g), p, res); });
+    collide_site_f<P, COMP, FORCE>(v, (C)omega, force,
+                                   [&](int p, C res) { P::template store<L::stream_stores>(st.own(buf, p, g), p, res); });
 }
 
 // Fused step src -> dst: pull the 37 populations, collide, store at the own
 // site. With AUDIT, the FP64 mass/momentum/energy of the stored result are
-// reduced per workgroup into partials[4 * tile]. With BC, the walls (if
-// bc.walls) replace the values pulled from beyond them, and the collide
-// applies the body force (zero force rounds exactly as without BC).
-template <class P, class L, bool COMP, bool AUDIT, bool BC>
+// reduced per workgroup into partials[4 * tile]. With FORCE, the collide
+// applies the body force (zero force rounds exactly as without it). Walls
+// need nothing here: k_wall has put their emission into the slots the pull
+// reads.
+template <class P, class L, bool COMP, bool AUDIT, bool FORCE>
 __global__ __launch_bounds__(BLOCK) void k_step(const typename P::T* __restrict__ src,
                                                 typename P::T* __restrict__ dst, Geo g, double omega,
-                                                double* __restrict__ partials, BcArgs<typename P::C> bc)
+                                                double* __restrict__ partials, Force<typename P::C> force)
 {
     using C = typename P::C;
     D2Q37_SITE(P, L);
@@ -304,18 +328,15 @@ __global__ __launch_bounds__(BLOCK) void k_step(const typename P::T* __restrict_
         C v[Q];
 #pragma unroll
         for (int p = 0; p < Q; ++p) v[p] = P::template load<L::stream_loads>(st.src(src, p, g), p);
-        if constexpr (BC) {
-            if (bc.walls) wall_emit<P>(v, st.x, st.y, g, bc);
-        }
         if constexpr (AUDIT) {
             double d[Q];
-            collide_site_f<P, COMP, BC>(v, (C)omega, bc.force, [&](int p, C res) {
+            collide_site_f<P, COMP, FORCE>(v, (C)omega, force, [&](int p, C res) {
                 P::template store<L::stream_stores>(st.own(dst, p, g), p, res);
                 d[p] = stored_as_f64<P>(res, p);
             });
             audit_site(d, acc);
         } else {
-            collide_site_f<P, COMP, BC>(v, (C)omega, bc.force, [&](int p, C res) {
+            collide_site_f<P, COMP, FORCE>(v, (C)omega, force, [&](int p, C res) {
                 P::template store<L::stream_stores>(st.own(dst, p, g), p, res);
             });
         }

@@ -34,10 +34,9 @@ struct lb_ctx {
     int lgrid;             // their persistent grid: min(tiles, compute units)
     int64_t audit_parts;   // partial sums written by the last fused audit
     bool fused_audit_valid;
-    bool bc;               // walls or a nonzero body force: the kernels' BC path
+    bool forced;           // nonzero body force: the collides' FORCE path
     double force[3];       // R tau gx, R tau gy, tau (1 - tau) |g|^2 / 2
     double* wall_tab;      // scratch: [2][WALL_TAB] (walls only)
-    double* rho_w;         // scratch: [2][lx] wall densities (FP32 for shifted storage)
     int device;            // device current at lb_init (where the buffers live)
     void* static_scratch;  // that device's address of `scratch` (lb_audit_static), or NULL
     char err[512];
@@ -134,28 +133,21 @@ int launch_status(lb_ctx* c, const char* what) { return check_hip(c, hipGetLastE
 dim3 grid_of(const lb_ctx* c) { return dim3((unsigned)c->nblocks); }
 
 template <typename C>
-BcArgs<C> bc_args(const lb_ctx* c)
+Force<C> force_of(const lb_ctx* c)
 {
-    BcArgs<C> b;
-    b.force.dUx = (C)c->force[0];
-    b.force.dUy = (C)c->force[1];
-    b.force.dt = (C)c->force[2];
-    b.walls = c->cfg.walls;
-    b.tab = c->wall_tab;
-    b.rho_w = (const C*)c->rho_w;
-    return b;
+    return Force<C>{(C)c->force[0], (C)c->force[1], (C)c->force[2]};
 }
 
-// Wall densities of the current buffer (before a propagate), walls only.
+// Walls: the emission of both walls into the current buffer's slots that
+// the next pull reads from beyond them (before a propagate or step).
 void launch_wall(lb_ctx* c)
 {
     with_config(c->cfg, [&](auto p, auto l) {
         using P = decltype(p);
         using L = decltype(l);
-        const int64_t threads = 2 * (int64_t)c->geo.lx;
-        hipLaunchKernelGGL((k_wall<P, L>), dim3((unsigned)div_up(threads, BLOCK)), dim3(BLOCK), 0, c->stream,
-                           (const typename P::T*)cur_buf(c), c->geo, (const double*)c->wall_tab,
-                           (typename P::C*)c->rho_w);
+        const int64_t blocks = div_up(c->geo.lx, BLOCK / 64);  // one wavefront per column
+        hipLaunchKernelGGL((k_wall<P, L>), dim3((unsigned)blocks), dim3(BLOCK), 0, c->stream,
+                           (typename P::T*)cur_buf(c), c->geo, (const double*)c->wall_tab);
     });
 }
 dim3 lgrid_of(const lb_ctx* c) { return dim3((unsigned)c->lgrid); }
@@ -247,10 +239,8 @@ size_t lb_scratch_bytes(int32_t lx, int32_t ly)
     const int64_t n = (int64_t)lx * ly;
     if (n >= ((int64_t)1 << 31)) return 0;
     // one partial sum of 4 doubles per row-tiled workgroup, the 4 totals, two
-    // 64-bit counters of the learned collide, the walls' table and their
-    // per-column densities
-    return round256((size_t)((int64_t)lx * div_up(ly, BLOCK) * 4 + 4 + 2 + 2 * WALL_TAB + 2 * (int64_t)lx) *
-                    sizeof(double));
+    // 64-bit counters of the learned collide and the walls' table
+    return round256((size_t)((int64_t)lx * div_up(ly, BLOCK) * 4 + 4 + 2 + 2 * WALL_TAB) * sizeof(double));
 }
 
 int lb_init(lb_ctx** out, const lb_config* cfg, const double* rho, const double* ux, const double* uy,
@@ -308,8 +298,7 @@ int lb_init(lb_ctx** out, const lb_config* cfg, const double* rho, const double*
     c->totals = c->partials + 4 * c->nblocks;
     c->counts = (unsigned long long*)(c->totals + 4);
     c->wall_tab = c->totals + 4 + 2;
-    c->rho_w = c->wall_tab + 2 * WALL_TAB;
-    c->bc = k.walls != 0 || k.gx != 0.0 || k.gy != 0.0;
+    c->forced = k.gx != 0.0 || k.gy != 0.0;
     c->force[0] = R * k.tau * k.gx;
     c->force[1] = R * k.tau * k.gy;
     c->force[2] = k.tau * (1.0 - k.tau) * (k.gx * k.gx + k.gy * k.gy) / 2.0;
@@ -356,13 +345,8 @@ int lb_propagate(lb_ctx* c)
     with_config(c->cfg, [&](auto p, auto l) {
         using P = decltype(p);
         using L = decltype(l);
-        const auto bc = bc_args<typename P::C>(c);
-        if (c->cfg.walls)
-            hipLaunchKernelGGL((k_propagate<P, L, true>), grid_of(c), dim3(BLOCK), 0, c->stream,
-                               (const typename P::Word*)cur_buf(c), (typename P::Word*)other_buf(c), c->geo, bc);
-        else
-            hipLaunchKernelGGL((k_propagate<P, L, false>), grid_of(c), dim3(BLOCK), 0, c->stream,
-                               (const typename P::Word*)cur_buf(c), (typename P::Word*)other_buf(c), c->geo, bc);
+        hipLaunchKernelGGL((k_propagate<P, L>), grid_of(c), dim3(BLOCK), 0, c->stream,
+                           (const typename P::Word*)cur_buf(c), (typename P::Word*)other_buf(c), c->geo);
     });
     const int rc = launch_status(c, "lb_propagate");
     if (rc != LB_OK) return rc;
@@ -391,14 +375,14 @@ int lb_collide(lb_ctx* c)
         with_config(c->cfg, [&](auto p, auto l) {
             using P = decltype(p);
             using L = decltype(l);
-            const auto bc = bc_args<typename P::C>(c);
+            const auto force = force_of<typename P::C>(c);
             auto* buf = (typename P::T*)cur_buf(c);
-#define D2Q37_COLL(CMP, BCF) \
-    hipLaunchKernelGGL((k_collide<P, L, CMP, BCF>), grid_of(c), dim3(BLOCK), 0, c->stream, buf, c->geo, omega, bc)
+#define D2Q37_COLL(CMP, FRC) \
+    hipLaunchKernelGGL((k_collide<P, L, CMP, FRC>), grid_of(c), dim3(BLOCK), 0, c->stream, buf, c->geo, omega, force)
             if (comp) {
-                if (c->bc) D2Q37_COLL(true, true); else D2Q37_COLL(true, false);
+                if (c->forced) D2Q37_COLL(true, true); else D2Q37_COLL(true, false);
             } else {
-                if (c->bc) D2Q37_COLL(false, true); else D2Q37_COLL(false, false);
+                if (c->forced) D2Q37_COLL(false, true); else D2Q37_COLL(false, false);
             }
 #undef D2Q37_COLL
         });
@@ -451,12 +435,12 @@ int lb_step(lb_ctx* c, int32_t nsteps)
             using L = decltype(l);
             const auto* src = (const typename P::T*)cur_buf(c);
             auto* dst = (typename P::T*)other_buf(c);
-            const auto bc = bc_args<typename P::C>(c);
-#define D2Q37_STEP(CMP, AUD, BCF)                                                                              \
-    hipLaunchKernelGGL((k_step<P, L, CMP, AUD, BCF>), grid_of(c), dim3(BLOCK), 0, c->stream, src, dst, c->geo, omega, \
-                       c->partials, bc)
+            const auto force = force_of<typename P::C>(c);
+#define D2Q37_STEP(CMP, AUD, FRC)                                                                              \
+    hipLaunchKernelGGL((k_step<P, L, CMP, AUD, FRC>), grid_of(c), dim3(BLOCK), 0, c->stream, src, dst, c->geo, omega, \
+                       c->partials, force)
 #define D2Q37_STEP_BC(CMP, AUD) \
-    do { if (c->bc) D2Q37_STEP(CMP, AUD, true); else D2Q37_STEP(CMP, AUD, false); } while (0)
+    do { if (c->forced) D2Q37_STEP(CMP, AUD, true); else D2Q37_STEP(CMP, AUD, false); } while (0)
             if (comp) {
                 if (audit) D2Q37_STEP_BC(true, true); else D2Q37_STEP_BC(true, false);
             } else {
@@ -550,7 +534,7 @@ int lb_set_surrogate(lb_ctx* c, const lb_mlp* m, double threshold)
     }
     if (c->cfg.precision != LB_FP32_SHIFTED)
         return fail(c, LB_EUNSUPPORTED, "lb_set_surrogate: the learned collide needs FP32-shifted populations");
-    if (c->bc)
+    if (c->forced || c->cfg.walls)
         return fail(c, LB_EUNSUPPORTED, "lb_set_surrogate: the learned collide runs on periodic lattices without force");
     if (!(threshold >= 0.0) || !std::isfinite(threshold))
         return fail(c, LB_EINVAL, "lb_set_surrogate: threshold %g must be finite and >= 0", threshold);

@@ -124,23 +124,6 @@ struct PrecF16S {
 template <class P>
 constexpr int vl_of() { return 128 / (int)sizeof(typename P::T); }
 
-// Storage bits of a compute value, and back (exactly as store and load
-// round it).
-template <class P>
-__device__ inline typename P::Word word_of(typename P::C v, int p)
-{
-    if constexpr (P::kind == PREC_F64) return (uint64_t)__double_as_longlong(v);
-    else if constexpr (P::kind == PREC_F32S) return __float_as_uint(v);
-    else return (uint16_t)__half_as_ushort(__float2half_rn(v * P::scale(p)));
-}
-template <class P>
-__device__ inline typename P::C value_of(typename P::Word w, int p)
-{
-    if constexpr (P::kind == PREC_F64) return __longlong_as_double((long long)w);
-    else if constexpr (P::kind == PREC_F32S) return __uint_as_float(w);
-    else return __half2float(__ushort_as_half(w)) * (1.0f / P::scale(p));
-}
-
 // ---- layout indexers -----------------------------------------------------
 
 __device__ inline int wrap_periodic(int v, int L)
