@@ -245,11 +245,31 @@ struct Verdict {
 };
 
 
+// Heat-flux weight of the conserved functions: sum_p w_p cx_p^2 |c_p|^2
+// (the same with cy by symmetry). The vector w_p (c0 + cx cx_p + cy cy_p +
+// cq |c_p|^2) of the conserved space has stress moments sum cx cy v = 0 and
+// sum (cx^2 - cy^2) v = 0 and heat-flux moments sum cx |c|^2 v = cx S,
+// sum cy |c|^2 v = cy S, by the lattice's symmetries.
+constexpr double heat_flux_weight()
+{
+    double s = 0.0;
+    for (int p = 0; p < Q; ++p) s += weight(p) * (double)(CX[p] * CX[p]) * (double)c2_of(p);
+    return s;
+}
+constexpr double HF_WEIGHT = heat_flux_weight();
+
 // Learned equilibrium gh of each lane's site from its populations g and the
 // network outputs staged by network_outputs: gh_p = d_p + P(g - d)_p with
 // d_p = w_p (mean_y + sd_y o_p) (folded: o_p w_p sd_y + w_p mean_y), so gh
-// has the mass, momentum and energy of g. Returns the fallback verdict: residual against the equilibrium stress
-// and heat flux of (rho, u, T), training box on rho, |u|, T.
+// has the mass, momentum and energy of g. Returns the fallback verdict:
+// residual of gh's stress and heat flux against the equilibrium values of
+// (rho, u, T), and the training box on rho, |u|, T.
+//
+// The moments of d and g are summed over opposite pairs (c_o = -c_i: even
+// moments take the pair sums, odd ones the differences), and gh's stress
+// and heat flux are those of d plus the conserved part's, which the
+// lattice's symmetries reduce to two terms (HF_WEIGHT); the conserved part
+// itself is formed per shell.
 __device__ inline Verdict learned_equilibrium(const float (&g)[Q], const Net& net, const uint16_t* X, float threshold,
                                               float (&gh)[Q])
 {
@@ -261,40 +281,64 @@ __device__ inline Verdict learned_equilibrium(const float (&g)[Q], const Net& ne
         const float4 r = row[q];
         o[4 * q] = r.x, o[4 * q + 1] = r.y, o[4 * q + 2] = r.z, o[4 * q + 3] = r.w;
     }
-    float d0 = 0.f, dx = 0.f, dy = 0.f, de = 0.f;
 #pragma unroll
-    for (int p = 0; p < Q; ++p) {
-        const float d = __builtin_fmaf(o[p], fy[128 + p], fy[192 + p]);
-        gh[p] = d;
-        d0 += d;
-        if (CX[p] != 0) dx = __builtin_fmaf((float)CX[p], d, dx);
-        if (CY[p] != 0) dy = __builtin_fmaf((float)CY[p], d, dy);
-        if (c2_of(p) != 0) de = __builtin_fmaf((float)c2_of(p), d, de);
-    }
-    const Conserved mg = conserved_moments(g);
-    const float md0 = d0, mdx = mulk(dx, R), mdy = mulk(dy, R), mdE = mulk(de, R2) - 2.0f * d0;
-    const ConservedCoef k = conserved_coef(mg.m0 - md0, mg.mx - mdx, mg.my - mdy, mg.mE - mdE);
+    for (int p = 0; p < Q; ++p) gh[p] = __builtin_fmaf(o[p], fy[128 + p], fy[192 + p]);  // d_p
 
-    const float rho = 1.0f + mg.m0;
-    const float ux = mg.mx / rho, uy = mg.my / rho;
-    const float u2 = ux * ux + uy * uy;
-    const float T = 1.0f + (mg.mE - rho * u2) / (2.0f * rho);
-    float sxy = 0.f, snn = 0.f, sqx = 0.f, sqy = 0.f;  // lattice units
+    float d0 = gh[REST], de = 0.f, dx = 0.f, dy = 0.f, sxy = 0.f, snn = 0.f, sqx = 0.f, sqy = 0.f;
+    float g0 = g[REST], ge = 0.f, gx = 0.f, gy = 0.f;
 #pragma unroll
-    for (int p = 0; p < Q; ++p) {
-        const float v = gh[p] + conserved_value(p, k);
-        gh[p] = v;
-        if (CX[p] * CY[p] != 0) sxy = __builtin_fmaf((float)(CX[p] * CY[p]), v, sxy);
-        if (CX[p] * CX[p] - CY[p] * CY[p] != 0)
-            snn = __builtin_fmaf((float)(CX[p] * CX[p] - CY[p] * CY[p]), v, snn);
-        if (CX[p] != 0) sqx = __builtin_fmaf((float)(CX[p] * c2_of(p)), v, sqx);
-        if (CY[p] != 0) sqy = __builtin_fmaf((float)(CY[p] * c2_of(p)), v, sqy);
+    for (int i = 0; i < NPAIR; ++i) {
+        const int op = Q - 1 - i;
+        const float ds = gh[i] + gh[op], dd = gh[i] - gh[op];
+        const float gs = g[i] + g[op], gd = g[i] - g[op];
+        const float c2 = (float)c2_of(i);
+        d0 += ds;
+        g0 += gs;
+        de = __builtin_fmaf(c2, ds, de);
+        ge = __builtin_fmaf(c2, gs, ge);
+        if (CX[i] != 0) {
+            dx = __builtin_fmaf((float)CX[i], dd, dx);
+            gx = __builtin_fmaf((float)CX[i], gd, gx);
+            sqx = __builtin_fmaf((float)(CX[i] * c2_of(i)), dd, sqx);
+        }
+        if (CY[i] != 0) {
+            dy = __builtin_fmaf((float)CY[i], dd, dy);
+            gy = __builtin_fmaf((float)CY[i], gd, gy);
+            sqy = __builtin_fmaf((float)(CY[i] * c2_of(i)), dd, sqy);
+        }
+        if (CX[i] * CY[i] != 0) sxy = __builtin_fmaf((float)(CX[i] * CY[i]), ds, sxy);
+        if (CX[i] * CX[i] != CY[i] * CY[i]) snn = __builtin_fmaf((float)(CX[i] * CX[i] - CY[i] * CY[i]), ds, snn);
     }
+    const float mgx = mulk(gx, R), mgy = mulk(gy, R), mgE = mulk(ge, R2) - 2.0f * g0;
+    const float mdx = mulk(dx, R), mdy = mulk(dy, R), mdE = mulk(de, R2) - 2.0f * d0;
+    const ConservedCoef k = conserved_coef(g0 - d0, mgx - mdx, mgy - mdy, mgE - mdE);
+
+    // gh = d + w_p (c0 + cx cx_p + cy cy_p + cq |c_p|^2), the products with
+    // w formed once per shell
+#pragma unroll
+    for (int h = 0; h < NSHELL; ++h) {
+        const float base = mulk(__builtin_fmaf(k.cq, (float)SHELL_C2[h], k.c0), WSH[h]);
+        const float xw = mulk(k.cx, WSH[h]), yw = mulk(k.cy, WSH[h]);
+#pragma unroll
+        for (int p = 0; p < Q; ++p) {
+            if (shell_of_c2(c2_of(p)) != h) continue;
+            float v = base;
+            if (CX[p] != 0) v = __builtin_fmaf((float)CX[p], xw, v);
+            if (CY[p] != 0) v = __builtin_fmaf((float)CY[p], yw, v);
+            gh[p] += v;
+        }
+    }
+
+    const float rho = 1.0f + g0;
+    const float inv_rho = 1.0f / rho;
+    const float ux = mgx * inv_rho, uy = mgy * inv_rho;
+    const float u2 = ux * ux + uy * uy;
+    const float T = 1.0f + (mgE - rho * u2) * (0.5f * inv_rho);
     const float q4 = u2 + 4.0f * T;
     const float r1 = fabsf(mulk(sxy, R2) - rho * ux * uy);
     const float r2 = fabsf(mulk(snn, R2) - rho * (ux * ux - uy * uy));
-    const float r3 = fabsf(mulk(sqx, R * R2) - rho * ux * q4);
-    const float r4 = fabsf(mulk(sqy, R * R2) - rho * uy * q4);
+    const float r3 = fabsf(mulk(sqx + mulk(k.cx, HF_WEIGHT), R * R2) - rho * ux * q4);
+    const float r4 = fabsf(mulk(sqy + mulk(k.cy, HF_WEIGHT), R * R2) - rho * uy * q4);
     Verdict vd;
     vd.residual = fmaxf(fmaxf(r1, r2), fmaxf(r3, r4));
     const bool in_box = rho >= 0.9f && rho <= 1.1f && u2 <= 0.01f && T >= 0.9f && T <= 1.1f;
