@@ -125,6 +125,35 @@ def bf16(x: np.ndarray) -> np.ndarray:
     return u.astype(np.uint32).view(np.float32).astype(np.float64)
 
 
+def e4m3(x) -> np.ndarray:
+    """Round to FP8 e4m3 (the OCP "fn" variant: 1 sign, 4 exponent bits with
+    bias 7, 3 mantissa bits, no infinities, largest finite value 448),
+    nearest with ties to an even mantissa; magnitudes that round beyond 448
+    become NaN (there is no saturation). Subnormals step by 2^-9."""
+    x = np.asarray(x, dtype=np.float64)
+    a = np.abs(x)
+    _, e = np.frexp(np.where(a > 0, a, 1.0))       # a = f 2^e, f in [0.5, 1)
+    quantum = np.ldexp(1.0, np.maximum(e - 1, -6) - 3)
+    r = np.rint(a / quantum) * quantum              # rint: ties to even
+    r = np.where(a > 0, r, 0.0)
+    out = np.copysign(r, x)
+    return np.where(r > 448.0, np.nan, out)
+
+
+# FP8 form of the hidden layer: its inputs h1 (first-layer activations) and
+# weights W2 are rounded to e4m3 after scaling by powers of two, h1 by
+# FP8_ACT_SCALE and W2 by 2^fp8_weight_exponent(W2), so that the largest
+# weight lands in [128, 256); products are summed in high precision and
+# divided by the scales again.
+FP8_ACT_SCALE = 16.0
+
+
+def fp8_weight_exponent(W2) -> int:
+    m = float(np.max(np.abs(np.asarray(W2, dtype=np.float64))))
+    _, e = np.frexp(m if m > 0 else 1.0)
+    return int(8 - e)
+
+
 def gelu(a):
     return a / (1.0 + np.exp(-2.0 * GELU_C * (a + GELU_A * a ** 3)))
 
@@ -167,13 +196,21 @@ def init_params(seed: int) -> np.ndarray:
     return theta
 
 
-def forward(theta, x_std, emulate=True):
+def forward(theta, x_std, emulate=True, fp8=False):
+    """Network outputs (standardised) and the intermediates. fp8: the hidden
+    layer's inputs and weights in e4m3 (FP8 form above), the rest in BF16
+    (emulate must be set)."""
     p = unpack(theta)
     q = bf16 if emulate else (lambda v: v)
     x = q(x_std)
     a1 = x @ q(p["W1"]).T + p["b1"]
-    h1 = q(gelu(a1))
-    a2 = h1 @ q(p["W2"]).T + p["b2"]
+    if fp8:
+        sw = 2.0 ** fp8_weight_exponent(p["W2"])
+        h1 = e4m3(gelu(a1) * FP8_ACT_SCALE) / FP8_ACT_SCALE
+        a2 = h1 @ (e4m3(p["W2"] * sw) / sw).T + p["b2"]
+    else:
+        h1 = q(gelu(a1))
+        a2 = h1 @ q(p["W2"]).T + p["b2"]
     h2 = q(gelu(a2))
     o = h2 @ q(p["W3"]).T + p["b3"]
     return o, (x, a1, h1, a2, h2)
@@ -279,22 +316,23 @@ def train(pre, post, tau, theta0, norm, batch, epochs, lr0, seed, emulate=True, 
 
 # ---- the learned collide --------------------------------------------------------------
 
-def surrogate_equilibrium(g, theta, norm, emulate=True):
+def surrogate_equilibrium(g, theta, norm, emulate=True, fp8=False):
     w = constants()["w"]
     zs = (g / w - norm[0]) / norm[1]
-    o, _ = forward(theta, zs, emulate)
+    o, _ = forward(theta, zs, emulate, fp8)
     d = w * (norm[2] + norm[3] * o)
     return conserved_part(g) + d - conserved_part(d)
 
 
-def surrogate_collide(g, tau, theta, norm, threshold, emulate=True):
+def surrogate_collide(g, tau, theta, norm, threshold, emulate=True, fp8=False):
     """Post-collision shifted populations, fallback flags and residuals of the
-    sites g (n, 37)."""
+    sites g (n, 37). A residual that is not a number (an FP8 activation out
+    of range) counts as above the threshold."""
     w = constants()["w"]
     rho, ux, uy, T = macro(g)
-    ghat = surrogate_equilibrium(g, theta, norm, emulate)
+    ghat = surrogate_equilibrium(g, theta, norm, emulate, fp8)
     res = residual(ghat, rho, ux, uy, T)
-    fb = (~in_box(rho, ux, uy, T)) | (res > threshold)
+    fb = (~in_box(rho, ux, uy, T)) | ~(res <= threshold)
     if fb.any():
         idx = np.where(fb)[0]
         exact = lbm.init(rho[idx, None], ux[idx, None], uy[idx, None], T[idx, None])[:, :, 0].T - w
@@ -353,3 +391,34 @@ def flip_bound(theta, norm, g) -> np.ndarray:
     proj = phi.T @ ((phi * w) @ v / np.diag(gram())[:, None])
     col = (v + proj).max(axis=0)                                        # per unit j, per unit ulp
     return (bf16_ulp(h2) * col).max(axis=1)
+
+
+def e4m3_ulp(v: np.ndarray) -> np.ndarray:
+    """Spacing of e4m3 values at |v|: 2^(e - 3) for 2^e <= |v| < 2^(e + 1),
+    e >= -6; 2^-9 below 2^-6."""
+    a = np.abs(np.asarray(v, dtype=np.float64))
+    e = np.floor(np.log2(np.where(a > 0, a, 1.0)))
+    return np.where(a >= 2.0 ** -6, 2.0 ** (e - 3), 2.0 ** -9)
+
+
+def fp8_flip_bound(theta, norm, g) -> np.ndarray:
+    """B1 per site for the FP8 form: the largest |change of g_hat_p| / w_p
+    that one e4m3 rounding flip of one hidden-layer input h1_j can cause,
+    to first order: a2 moves by W2q[:, j] ulp(h1_j), h2 by at most
+    max|gelu'| times that, and h2 reaches g_hat as in flip_bound. Returns
+    (n,). (A flip also changes which way some h2 round to BF16; those are
+    second-layer flips, bounded by flip_bound.)"""
+    w = constants()["w"]
+    p = unpack(theta)
+    sw = 2.0 ** fp8_weight_exponent(p["W2"])
+    W2q = np.abs(e4m3(p["W2"] * sw) / sw)                               # (128 out, 128 in)
+    W3 = np.abs(bf16(p["W3"]))
+    zs = (np.asarray(g, dtype=np.float64) / w - norm[0]) / norm[1]
+    _, (_, _, h1, _, _) = forward(theta, zs, emulate=True, fp8=True)
+    v = np.asarray(norm[3], dtype=np.float64)[:, None] * W3
+    phi = np.abs(_basis())
+    proj = phi.T @ ((phi * w) @ v / np.diag(gram())[:, None])
+    col = (v + proj).max(axis=0)                                        # per second-layer unit
+    per_input = gelu_grad_max() * (col @ W2q)                           # per first-layer unit j
+    ulp = e4m3_ulp(h1 * FP8_ACT_SCALE) / FP8_ACT_SCALE
+    return (ulp * per_input).max(axis=1)

@@ -218,3 +218,117 @@ def test_flip_bound_covers_single_flips_anywhere(consts, trained):
         h2_ratio.append(worst["h2"] / B2)
     assert max(ratio.values()) <= 4.0, ratio
     assert np.median(h2_ratio) >= 1 / 3, h2_ratio
+
+
+# ---- FP8 (e4m3) form of the hidden layer -------------------------------------------
+
+def _e4m3_codes():
+    """Every e4m3 code decoded by the format's definition (OCP FP8 "E4M3",
+    the variant without infinities): sign bit, exponent field E (bias 7),
+    mantissa field M (3 bits); E = 0 subnormal M 2^-9; E = 15, M = 7 is NaN.
+    Returns {code: value} for the finite codes."""
+    out = {}
+    for code in range(256):
+        sgn = -1.0 if code & 0x80 else 1.0
+        E, M = (code >> 3) & 0xF, code & 0x7
+        if E == 15 and M == 7:
+            continue
+        out[code] = sgn * (M * 2.0 ** -9 if E == 0 else (1 + M / 8) * 2.0 ** (E - 7))
+    return out
+
+
+def test_e4m3_rounding_against_the_format_definition():
+    """Finite codes are fixed points; any value goes to the nearest finite
+    code (a tie to the code with an even mantissa field); values beyond the
+    midpoint of 448 and the next (would-be) step 480 are NaN."""
+    codes = _e4m3_codes()
+    assert max(codes.values()) == 448.0 and min(v for v in codes.values() if v > 0) == 2.0 ** -9
+    vals = np.array(list(codes.values()))
+    assert np.array_equal(S.e4m3(vals), vals)
+    pos = sorted(set(abs(v) for v in codes.values()))
+    even = {abs(v): (c & 1) == 0 for c, v in codes.items()}
+    rng = np.random.default_rng(5)
+    x = np.concatenate([rng.uniform(-470, 470, 4000), rng.normal(0, 1, 4000), rng.normal(0, 0.01, 2000),
+                        [(a + b) / 2 for a, b in zip(pos, pos[1:])], [463.99, 464.0, 464.01, 479.0, 1e6]])
+    got = S.e4m3(x)
+    for xi, gi in zip(x, got):
+        a = abs(xi)
+        if a > 464.0:
+            assert np.isnan(gi), xi
+            continue
+        d = [abs(a - v) for v in pos]
+        best = min(d)
+        near = [v for v, dv in zip(pos, d) if dv == best]
+        want = near[0] if len(near) == 1 else [v for v in near if even[v]][0]
+        assert abs(gi) == want and (gi == 0 or np.sign(gi) == np.sign(xi)), (xi, gi, want)
+
+
+def test_e4m3_worked_values():
+    """Values worked out by hand from the format: 0.3 -> 1.25 x 2^-2; 449 and
+    464 -> 448 (464 is a tie, 448's mantissa field 6 is even); 470 -> NaN;
+    1.5 x 2^-9 and 2.5 x 2^-9 -> 2^-8 (ties to the even subnormal 2); 1e-5
+    -> 0."""
+    x = np.array([0.3, 449.0, 464.0, 470.0, 1.5 * 2 ** -9, 2.5 * 2 ** -9, 1e-5, -1.75, 240.0])
+    want = np.array([0.3125, 448.0, 448.0, np.nan, 2 ** -8, 2 ** -8, 0.0, -1.75, 240.0])
+    assert np.array_equal(S.e4m3(x), want, equal_nan=True)
+
+
+def test_fp8_weight_exponent_puts_the_largest_weight_in_128_256():
+    rng = np.random.default_rng(1)
+    for scale in (1e-3, 0.09, 0.2, 0.5, 3.0):
+        W = scale * rng.standard_normal((128, 128))
+        m = np.abs(W).max() * 2.0 ** S.fp8_weight_exponent(W)
+        assert 128.0 <= m < 256.0
+
+
+def test_fp8_forward_rounds_only_the_hidden_layer():
+    """The FP8 form keeps the first layer and its inputs (BF16), puts the
+    hidden layer's inputs on the e4m3 grid (scaled by 16) and differs from
+    the BF16 form by about the e4m3 rounding (3 mantissa bits)."""
+    tau = 0.8
+    pre, post = S.make_pairs(512, seed=3, tau=tau)
+    norm = S.fit_normalization(pre, post, tau)
+    theta = S.init_params(2)
+    zs = (pre / S.constants()["w"] - norm[0]) / norm[1]
+    o8, (x8, a18, h18, _, _) = S.forward(theta, zs, emulate=True, fp8=True)
+    o16, (x16, a116, h116, _, _) = S.forward(theta, zs, emulate=True)
+    assert np.array_equal(x8, x16) and np.array_equal(a18, a116)
+    assert np.array_equal(S.e4m3(h18 * S.FP8_ACT_SCALE) / S.FP8_ACT_SCALE, h18)
+    rel = np.abs(o8 - o16).max() / np.abs(o16).max()
+    assert 1e-4 < rel < 0.2, rel
+
+
+def test_fp8_flip_bound_covers_planted_flips(consts):
+    """One e4m3 flip (one step of the grid, either direction) of one
+    hidden-layer input, everything downstream rounded again: g_hat moves by
+    at most B1 + 8 B2 of the site (B2: the BF16 re-roundings it triggers)."""
+    w = consts["w"]
+    tau = 0.8
+    pre, post = S.make_pairs(1024, seed=22, tau=tau)
+    norm = S.fit_normalization(pre, post, tau)
+    theta = S.init_params(6)
+    sites = pre[::67]
+    B1 = S.fp8_flip_bound(theta, norm, sites)
+    B2 = S.flip_bound(theta, norm, sites)
+    p = S.unpack(theta)
+    sw = 2.0 ** S.fp8_weight_exponent(p["W2"])
+    W2q = S.e4m3(p["W2"] * sw) / sw
+    W3 = S.bf16(p["W3"])
+    zs = (sites / w - norm[0]) / norm[1]
+    _, (_, _, h1, _, _) = S.forward(theta, zs, emulate=True, fp8=True)
+    rng = np.random.default_rng(2)
+
+    def ghat(g, h1row):
+        h2 = S.bf16(S.gelu(h1row @ W2q.T + p["b2"]))
+        d = w * (norm[2] + norm[3] * (h2 @ W3.T + p["b3"]))
+        return S.conserved_part(g) + d - S.conserved_part(d)
+
+    worst = 0.0
+    for i, g in enumerate(sites):
+        base = ghat(g[None, :], h1[i:i + 1])
+        for j in range(128):
+            v = h1[i:i + 1].copy()
+            v[0, j] += rng.choice([-1.0, 1.0]) * S.e4m3_ulp(v[0, j] * S.FP8_ACT_SCALE) / S.FP8_ACT_SCALE
+            moved = ghat(g[None, :], v)
+            worst = max(worst, float(np.max(np.abs(moved - base) / w) / (B1[i] + 8 * B2[i])))
+    assert worst <= 1.0, worst
