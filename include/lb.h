@@ -310,6 +310,25 @@ int lb_mlp_gradient(lb_mlp *m, const float *pre, const float *post, int32_t n, d
 int lb_mlp_train(lb_mlp *m, const float *pre, const float *post, int64_t n, double tau, int32_t batch,
                  int32_t epochs, float lr, uint64_t seed, int64_t max_steps, double *host_epoch_loss);
 
+/* Precision of the network's inference (the learned collide and
+ * lb_mlp_equilibrium; training is always BF16 with FP32 accumulation):
+ *   LB_MLP_BF16  every layer BF16 x BF16 -> FP32 (the default);
+ *   LB_MLP_FP8   the hidden 128 x 128 layer in FP8 (e4m3, the OCP variant
+ *                without infinities): its inputs, the first layer's GELU
+ *                outputs, scaled by 16, and its weights, scaled by 2^aw
+ *                with aw the exponent that puts max |W2| in [128, 256),
+ *                both rounded to nearest even, products accumulated in
+ *                FP32 by the FP8 matrix instructions; the first and last
+ *                layers stay BF16. A scaled activation beyond 448 becomes
+ *                NaN and its site falls back to the plain collide.
+ * lb_mlp_set_precision makes the FP8 copies from the current parameters
+ * (again after every lb_mlp_init, _set_params and _train while FP8 is set).
+ * LB_EINVAL for a NULL network or an unknown precision. (Not in the paper:
+ * a lower-precision variant of the learned collide.) */
+enum { LB_MLP_BF16 = 0, LB_MLP_FP8 = 1 };
+int lb_mlp_set_precision(lb_mlp *m, int32_t precision);
+int lb_mlp_get_precision(const lb_mlp *m);
+
 /* Learned equilibrium g_hat of n device sites pre[n][37] (plain equilibrium
  * where the verdict is fallback); residual[n] (FP32) and fallback[n] (int32,
  * 1 = fallback) may be NULL. Device outputs. */

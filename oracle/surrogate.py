@@ -357,7 +357,7 @@ def gelu_grad_max() -> float:
     return float(np.abs(gelu_grad(a)).max()) + 1e-6
 
 
-def flip_bound(theta, norm, g) -> np.ndarray:
+def flip_bound(theta, norm, g, fp8=False) -> np.ndarray:
     """B2 per site: the largest |change of g_hat_p| / w_p over populations
     that one BF16 rounding flip of one second-layer activation can cause at
     each of the sites g (n, 37): h2_j rounded to the neighbouring BF16 value,
@@ -376,7 +376,8 @@ def flip_bound(theta, norm, g) -> np.ndarray:
       |dg_hat_p| / w_p <= sd_y,p |do_p|
                           + sum_a |phi_a(p)| sum_q w_q sd_y,q |do_q| |phi_a(q)| / G_aa
     (P: the projection onto the conserved functions phi, Gram diagonal
-    G_aa), maximised over p and j with W3 at its BF16 values. A flip of an
+    G_aa), maximised over p and j with W3 at its BF16 values (fp8: the
+    second-layer activations of the FP8 form). A flip of an
     input or of a first-layer activation reaches the output through the
     next layers and through the roundings it changes there; planted on this
     forward pass (over every unit, at sampled sites) it moves g_hat by at
@@ -385,7 +386,7 @@ def flip_bound(theta, norm, g) -> np.ndarray:
     p = unpack(theta)
     W3 = np.abs(bf16(p["W3"]))
     zs = (np.asarray(g, dtype=np.float64) / w - norm[0]) / norm[1]
-    _, (_, _, _, _, h2) = forward(theta, zs, emulate=True)
+    _, (_, _, _, _, h2) = forward(theta, zs, emulate=True, fp8=fp8)
     v = np.asarray(norm[3], dtype=np.float64)[:, None] * W3          # (37 outputs, 128 units)
     phi = np.abs(_basis())
     proj = phi.T @ ((phi * w) @ v / np.diag(gram())[:, None])

@@ -362,14 +362,18 @@ int lb_collide(lb_ctx* c)
     const double omega = 1.0 / c->cfg.tau;
     const bool comp = c->cfg.compensated != 0;
     if (c->mlp) {
+        const bool fp8 = c->mlp->precision == LB_MLP_FP8;
         with_layout<PrecF32S>(c->cfg.layout, [&](auto, auto l) {
             using L = decltype(l);
-            if (comp)
-                hipLaunchKernelGGL((k_collide_learned<L, true>), lgrid_of(c), dim3(LBLOCK), 0, c->stream,
-                                   (float*)cur_buf(c), c->lgeo, omega, c->mlp->net(), c->threshold, c->counts);
-            else
-                hipLaunchKernelGGL((k_collide_learned<L, false>), lgrid_of(c), dim3(LBLOCK), 0, c->stream,
-                                   (float*)cur_buf(c), c->lgeo, omega, c->mlp->net(), c->threshold, c->counts);
+#define D2Q37_LCOLL(CMP, F8)                                                                                       \
+    hipLaunchKernelGGL((k_collide_learned<L, CMP, F8>), lgrid_of(c), dim3(LBLOCK), 0, c->stream, (float*)cur_buf(c), \
+                       c->lgeo, omega, c->mlp->net(), c->threshold, c->counts)
+            if (comp) {
+                if (fp8) D2Q37_LCOLL(true, true); else D2Q37_LCOLL(true, false);
+            } else {
+                if (fp8) D2Q37_LCOLL(false, true); else D2Q37_LCOLL(false, false);
+            }
+#undef D2Q37_LCOLL
         });
     } else {
         with_config(c->cfg, [&](auto p, auto l) {
@@ -411,14 +415,18 @@ int lb_step(lb_ctx* c, int32_t nsteps)
                 using L = decltype(l);
                 const float* src = (const float*)cur_buf(c);
                 float* dst = (float*)other_buf(c);
-#define D2Q37_LSTEP(CMP, AUD)                                                                                  \
-    hipLaunchKernelGGL((k_step_learned<L, CMP, AUD>), lgrid_of(c), dim3(LBLOCK), 0, c->stream, src, dst, c->lgeo, \
+                const bool fp8 = c->mlp->precision == LB_MLP_FP8;
+#define D2Q37_LSTEP(CMP, AUD, F8)                                                                                  \
+    hipLaunchKernelGGL((k_step_learned<L, CMP, AUD, F8>), lgrid_of(c), dim3(LBLOCK), 0, c->stream, src, dst, c->lgeo, \
                        omega, c->mlp->net(), c->threshold, c->partials, c->counts)
+#define D2Q37_LSTEP8(CMP, AUD) \
+    do { if (fp8) D2Q37_LSTEP(CMP, AUD, true); else D2Q37_LSTEP(CMP, AUD, false); } while (0)
                 if (comp) {
-                    if (audit) D2Q37_LSTEP(true, true); else D2Q37_LSTEP(true, false);
+                    if (audit) D2Q37_LSTEP8(true, true); else D2Q37_LSTEP8(true, false);
                 } else {
-                    if (audit) D2Q37_LSTEP(false, true); else D2Q37_LSTEP(false, false);
+                    if (audit) D2Q37_LSTEP8(false, true); else D2Q37_LSTEP8(false, false);
                 }
+#undef D2Q37_LSTEP8
 #undef D2Q37_LSTEP
             });
             const int rc = launch_status(c, "lb_step (learned collide)");

@@ -129,13 +129,13 @@ __device__ inline void finish_learned(LearnedLds& S, double (&acc)[4], unsigned 
 // current buffer (src == dst, each site's own populations); otherwise the
 // fused step src -> dst (pulled populations). With AUDIT,
 // partials[4 * blockIdx.x ..] receive the workgroup's FP64 sums.
-template <class L, bool COMP, bool AUDIT, bool INPLACE>
+template <class L, bool COMP, bool AUDIT, bool INPLACE, bool FP8>
 __device__ inline void learned_tiles(LearnedLds& S, const mlp::Net& gnet, const float* src, float* dst, const Geo& g,
                                      float om, float threshold, double* partials, unsigned long long* counts)
 {
     using P = PrecF32S;
     constexpr int VL = vl_of<P>();
-    const mlp::Net net = mlp::share_weights<LBLOCK>(gnet, S.w);
+    const mlp::Net net = mlp::share_weights<LBLOCK, FP8>(gnet, S.w);
     __syncthreads();
     uint16_t* X = S.X[threadIdx.x >> 6];
     uint32_t* q = S.fq[threadIdx.x >> 6];
@@ -159,7 +159,7 @@ __device__ inline void learned_tiles(LearnedLds& S, const mlp::Net& gnet, const 
             for (int p = 0; p < Q; ++p) in[p] = P::template load<false>(at(p), p);
             mlp::stage_inputs(X, net, in);
         }
-        mlp::network_outputs(net, X);
+        mlp::network_outputs<FP8>(net, X);
         // second gather: the populations for projection and relaxation
         float v[Q];
 #pragma unroll
@@ -191,24 +191,24 @@ __device__ inline void learned_tiles(LearnedLds& S, const mlp::Net& gnet, const 
 }
 
 // Fused step src -> dst with the learned collide; g.tpr counts 512-site
-// tiles per row here.
-template <class L, bool COMP, bool AUDIT>
+// tiles per row here. FP8: the network's hidden layer in e4m3.
+template <class L, bool COMP, bool AUDIT, bool FP8>
 __global__ __launch_bounds__(LBLOCK) __attribute__((amdgpu_waves_per_eu(2, 2))) void k_step_learned(
     const float* __restrict__ src, float* __restrict__ dst, Geo g, double omega, mlp::Net gnet, float threshold,
     double* __restrict__ partials, unsigned long long* __restrict__ counts)
 {
     __shared__ LearnedLds S;
-    learned_tiles<L, COMP, AUDIT, false>(S, gnet, src, dst, g, (float)omega, threshold, partials, counts);
+    learned_tiles<L, COMP, AUDIT, false, FP8>(S, gnet, src, dst, g, (float)omega, threshold, partials, counts);
 }
 
 // In-place learned collide on the current buffer (same walk).
-template <class L, bool COMP>
+template <class L, bool COMP, bool FP8>
 __global__ __launch_bounds__(LBLOCK) __attribute__((amdgpu_waves_per_eu(2, 2))) void k_collide_learned(
     float* __restrict__ buf, Geo g, double omega, mlp::Net gnet, float threshold,
     unsigned long long* __restrict__ counts)
 {
     __shared__ LearnedLds S;
-    learned_tiles<L, COMP, false, true>(S, gnet, buf, buf, g, (float)omega, threshold, nullptr, counts);
+    learned_tiles<L, COMP, false, true, FP8>(S, gnet, buf, buf, g, (float)omega, threshold, nullptr, counts);
 }
 
 }  // namespace d2q37

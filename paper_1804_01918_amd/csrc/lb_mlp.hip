@@ -143,6 +143,50 @@ __global__ __launch_bounds__(TB) void k_mlp_pack(const float* __restrict__ param
     }
 }
 
+// The FP8 form's scaled copies (see Net), one workgroup: the exponent aw
+// puts max |W2| in [128, 256) (max |W2| = f 2^e, f in [0.5, 1): aw = 8 - e).
+__global__ __launch_bounds__(TB) void k_mlp_pack_fp8(const float* __restrict__ params, uint16_t* __restrict__ W1s,
+                                                     uint8_t* __restrict__ W2q, uint16_t* __restrict__ W3s,
+                                                     float* __restrict__ b1s, float* __restrict__ b2s,
+                                                     float* __restrict__ gk2)
+{
+    __shared__ float red[TB];
+    const int tid = threadIdx.x;
+    float mx = 0.0f;
+    for (int i = tid; i < HID * HID; i += TB) mx = fmaxf(mx, fabsf(params[OFF_W2 + i]));
+    red[tid] = mx;
+    __syncthreads();
+    for (int half = TB / 2; half > 0; half >>= 1) {
+        if (tid < half) red[tid] = fmaxf(red[tid], red[tid + half]);
+        __syncthreads();
+    }
+    int e = 0;
+    frexpf(red[0] > 0.0f ? red[0] : 1.0f, &e);
+    const int aw = 8 - e;
+    const float sw = ldexpf(1.0f, aw);
+    const float s3 = ldexpf(1.0f, -(aw + 4));  // 1 / (2^aw FP8_ACT_SCALE)
+    for (int i = tid; i < HID * HID; i += TB) {  // W2q[h2][slot]
+        const int a = i / HID, slot = i % HID;
+        W2q[i] = (uint8_t)(pack_fp8<false>(params[OFF_W2 + a * HID + chain_hidden(slot)] * sw, 0.0f, 0u) & 0xFFu);
+    }
+    for (int i = tid; i < HID * KIN; i += TB) {  // W1s[h][f]
+        const int h = i / KIN, f = i % KIN;
+        W1s[i] = f < Q ? bf16_bits(FP8_ACT_SCALE * params[OFF_W1 + h * Q + f]) : 0;
+    }
+    for (int i = tid; i < NOUT * HID; i += TB) {  // W3s[o][slot]
+        const int o = i / HID, slot = i % HID;
+        W3s[i] = o < Q ? bf16_bits(s3 * params[OFF_W3 + o * HID + chain_hidden(slot)]) : 0;
+    }
+    for (int i = tid; i < HID; i += TB) {
+        b1s[i] = FP8_ACT_SCALE * params[OFF_B1 + i];
+        b2s[i] = params[OFF_B2 + i] / s3;
+    }
+    if (tid == 0) {
+        gk2[0] = GELU_K1 * (s3 * s3 * s3);
+        gk2[1] = GELU_K2 * s3;
+    }
+}
+
 // Per-feature sums over the pairs (pass 0: values; pass 1: squared
 // deviations from `mean`), FP64, fixed order: block partials then a final sum.
 constexpr int STAT_TILE = 128;
@@ -491,6 +535,7 @@ __global__ __launch_bounds__(TB) void k_mlp_update(float* __restrict__ params, f
 
 // Learned equilibrium of n shifted-population sites (one per lane), with the
 // plain equilibrium where the verdict is fallback.
+template <bool FP8>
 __global__ __launch_bounds__(TB) __attribute__((amdgpu_waves_per_eu(2, 2))) void k_mlp_eval(const float* __restrict__ pre, int64_t n, Net net, float threshold,
                                                  float* __restrict__ geq, float* __restrict__ res,
                                                  int32_t* __restrict__ fb)
@@ -505,7 +550,7 @@ __global__ __launch_bounds__(TB) __attribute__((amdgpu_waves_per_eu(2, 2))) void
         for (int p = 0; p < Q; ++p) in[p] = active ? pre[s * Q + p] : 0.0f;
         stage_inputs(X, net, in);
     }
-    network_outputs(net, X);
+    network_outputs<FP8>(net, X);
     float g[Q];
 #pragma unroll
     for (int p = 0; p < Q; ++p) g[p] = active ? pre[s * Q + p] : 0.0f;
@@ -553,7 +598,8 @@ int fold_norm(lb_mlp* m)
 }
 
 struct WsLayout {
-    size_t params, m, v, W1b, W2b, W3b, W2t, W3t, W2p, W3p, norm, fnorm, partials, lossp, loss_epoch, stats, grad, total;
+    size_t params, m, v, W1b, W2b, W3b, W2t, W3t, W2p, W3p, W1s, W2q, W3s, b1s, b2s, gk2, norm, fnorm, partials, lossp,
+        loss_epoch, stats, grad, total;
 };
 
 WsLayout workspace_layout(int max_batch)
@@ -576,6 +622,12 @@ WsLayout workspace_layout(int max_batch)
     l.W3t = take(HID * KIN * 2);
     l.W2p = take(HID * HID * 2);
     l.W3p = take(NOUT * HID * 2);
+    l.W1s = take(HID * KIN * 2);
+    l.W2q = take(HID * HID);
+    l.W3s = take(NOUT * HID * 2);
+    l.b1s = take(HID * 4);
+    l.b2s = take(HID * 4);
+    l.gk2 = take(16 * 4);
     l.norm = take(4 * 64 * 4);
     l.fnorm = take(4 * 64 * 4);
     l.partials = take((size_t)max_wg * NPARAM_PAD * 4);
@@ -587,11 +639,22 @@ WsLayout workspace_layout(int max_batch)
     return l;
 }
 
+int launch_pack_fp8(lb_mlp* m)
+{
+    hipLaunchKernelGGL(k_mlp_pack_fp8, dim3(1), dim3(TB), 0, m->stream, m->params, m->W1s, m->W2q, m->W3s, m->b1s,
+                       m->b2s, m->gk2);
+    return mcheck(m, "FP8 pack");
+}
+
+// Operand copies of the parameters: the BF16 ones, and the FP8 form's when
+// the network evaluates in it.
 int launch_pack(lb_mlp* m)
 {
     hipLaunchKernelGGL(k_mlp_pack, dim3((HID * HID + TB - 1) / TB), dim3(TB), 0, m->stream, m->params, m->W1b, m->W2b,
                        m->W3b, m->W2t, m->W3t, m->W2p, m->W3p);
-    return mcheck(m, "pack");
+    const int rc = mcheck(m, "pack");
+    if (rc != LB_OK || m->precision != LB_MLP_FP8) return rc;
+    return launch_pack_fp8(m);
 }
 
 int reset_adam(lb_mlp* m)
@@ -691,6 +754,13 @@ int lb_mlp_create(lb_mlp** out, void* workspace, size_t bytes, int32_t max_batch
     m->W3t = (uint16_t*)(ws + l.W3t);
     m->W2p = (uint16_t*)(ws + l.W2p);
     m->W3p = (uint16_t*)(ws + l.W3p);
+    m->W1s = (uint16_t*)(ws + l.W1s);
+    m->W2q = (uint8_t*)(ws + l.W2q);
+    m->W3s = (uint16_t*)(ws + l.W3s);
+    m->b1s = (float*)(ws + l.b1s);
+    m->b2s = (float*)(ws + l.b2s);
+    m->gk2 = (float*)(ws + l.gk2);
+    m->precision = LB_MLP_BF16;
     m->norm = (float*)(ws + l.norm);
     m->fnorm = (float*)(ws + l.fnorm);
     m->partials = (float*)(ws + l.partials);
@@ -876,6 +946,11 @@ int lb_mlp_train(lb_mlp* m, const float* pre, const float* post, int64_t n, doub
             ++step;
         }
     }
+    // the updates refresh the BF16 copies; the FP8 form's are made once at the end
+    if (m->precision == LB_MLP_FP8) {
+        const int rc = launch_pack_fp8(m);
+        if (rc != LB_OK) return rc;
+    }
     if (host_epoch_loss) {
         double* hl = new (std::nothrow) double[(size_t)epochs * 2];
         if (!hl) return mfail(m, LB_EINVAL, "lb_mlp_train: out of host memory");
@@ -894,10 +969,25 @@ int lb_mlp_equilibrium(lb_mlp* m, const float* pre, int64_t n, float threshold, 
 {
     if (!m || !pre || !geq || n < 0) return mfail(m, LB_EINVAL, "lb_mlp_equilibrium: bad argument");
     if (n == 0) return LB_OK;
-    hipLaunchKernelGGL(k_mlp_eval, dim3((unsigned)((n + TB - 1) / TB)), dim3(TB), 0, m->stream, pre, n, m->net(),
-                       threshold, geq, residual, fallback);
+    if (m->precision == LB_MLP_FP8)
+        hipLaunchKernelGGL(k_mlp_eval<true>, dim3((unsigned)((n + TB - 1) / TB)), dim3(TB), 0, m->stream, pre, n,
+                           m->net(), threshold, geq, residual, fallback);
+    else
+        hipLaunchKernelGGL(k_mlp_eval<false>, dim3((unsigned)((n + TB - 1) / TB)), dim3(TB), 0, m->stream, pre, n,
+                           m->net(), threshold, geq, residual, fallback);
     return mcheck(m, "lb_mlp_equilibrium");
 }
+
+int lb_mlp_set_precision(lb_mlp* m, int32_t precision)
+{
+    if (!m) return mfail(nullptr, LB_EINVAL, "lb_mlp_set_precision: NULL network");
+    if (precision != LB_MLP_BF16 && precision != LB_MLP_FP8)
+        return mfail(m, LB_EINVAL, "lb_mlp_set_precision: unknown precision %d", precision);
+    m->precision = precision;
+    return precision == LB_MLP_FP8 ? launch_pack_fp8(m) : LB_OK;
+}
+
+int lb_mlp_get_precision(const lb_mlp* m) { return m ? m->precision : LB_EINVAL; }
 
 int lb_pairgen(float* pre, float* post, int64_t n, uint64_t seed, double tau, void* stream)
 {

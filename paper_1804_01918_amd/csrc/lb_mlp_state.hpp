@@ -25,6 +25,14 @@ struct lb_mlp {
     uint16_t* W3t;
     uint16_t* W2p;
     uint16_t* W3p;
+    // FP8 form of the hidden layer (Net): scaled copies, made from params
+    uint16_t* W1s;
+    uint8_t* W2q;
+    uint16_t* W3s;
+    float* b1s;
+    float* b2s;
+    float* gk2;
+    int32_t precision;    // LB_MLP_BF16 or LB_MLP_FP8
     float* norm;          // [4][64]
     float* fnorm;         // [4][64], folded from norm for inference (Net::fnorm)
     float* partials;      // [max_wg][NPARAM_PAD]
@@ -45,6 +53,12 @@ struct lb_mlp {
         n.W3t = W3t;
         n.W2p = W2p;
         n.W3p = W3p;
+        n.W1s = W1s;
+        n.W2q = W2q;
+        n.W3s = W3s;
+        n.b1s = b1s;
+        n.b2s = b2s;
+        n.gk2 = gk2;
         n.params = params;
         n.norm = norm;
         n.fnorm = fnorm;

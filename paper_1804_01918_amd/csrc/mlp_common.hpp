@@ -94,6 +94,35 @@ __device__ inline f32x4 mfma(bf16x8 a, bf16x8 b, f32x4 c)
     return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
 }
 
+// FP8 (e4m3, the OCP variant without infinities) tiles:
+// v_mfma_f32_16x16x32_fp8_fp8 has the lane layout above with eight one-byte
+// values per lane (one 64-bit register pair per operand).
+__device__ inline f32x4 mfma_fp8(uint64_t a, uint64_t b, f32x4 c)
+{
+    return __builtin_amdgcn_mfma_f32_16x16x32_fp8_fp8((long)a, (long)b, c, 0, 0, 0);
+}
+// Fragment of a byte matrix stored index-major (ld and k0 multiples of 8).
+__device__ inline uint64_t frag8_im(const uint8_t* base, int ld, int i0, int k0)
+{
+    const int l = lane_id();
+    return *(const uint64_t*)(base + (i0 + (l & 15)) * ld + k0 + 8 * (l >> 4));
+}
+// Two FP32 values rounded to e4m3 (nearest even; beyond the largest finite
+// value, 448, the result is NaN), into bytes 2 HI, 2 HI + 1 of `old`.
+template <bool HI>
+__device__ inline uint32_t pack_fp8(float a, float b, uint32_t old)
+{
+    return (uint32_t)__builtin_amdgcn_cvt_pk_fp8_f32(a, b, (int)old, HI);
+}
+
+// FP8 form of the hidden layer (inference only): its inputs, the GELU
+// outputs of the first layer, are scaled by FP8_ACT_SCALE and its weights
+// W2 by 2^aw (aw: the largest weight lands in [128, 256)), both rounded to
+// e4m3; the product's scale 2^(aw + 4) is carried by copies of W1, b1, b2,
+// W3 and by the GELU constants, all scaled by powers of two, so that no
+// operation is added and every rounding is that of the unscaled form.
+constexpr float FP8_ACT_SCALE = 16.0f;
+
 // Register chaining of layers (inference). Computing a layer transposed,
 // H^T (hidden x sites) = W x X^T, each lane ends with 4 consecutive hidden
 // units of one site per 16-row tile; two tiles (hidden 16 apart) fill the 8
@@ -126,6 +155,17 @@ struct Net {
     const float* fnorm;   // [4][64] folded for inference: 1/(sd_z w), -mean_z/sd_z, w sd_y, w mean_y
     int ld1 = KIN;        // row strides of W1b and of W2p / W3p (the LDS copies are padded)
     int ld23 = HID;
+    // FP8 form: W1 x 16 (BF16 [128][64]), W2 x 2^aw (e4m3 [128][128], chained
+    // columns as W2p), W3 x 2^-(aw + 4) (BF16 [48][128], as W3p), b1 x 16,
+    // b2 x 2^(aw + 4), and the second GELU's constants for inputs scaled by
+    // 2^(aw + 4): {K1 2^-3(aw + 4), K2 2^-(aw + 4)}
+    const uint16_t* W1s = nullptr;
+    const uint8_t* W2q = nullptr;
+    const uint16_t* W3s = nullptr;
+    const float* b1s = nullptr;
+    const float* b2s = nullptr;
+    const float* gk2 = nullptr;
+    int ldq = HID;        // row stride of W2q in bytes
 };
 
 // ---- conserved part and residual of shifted populations -----------------------

@@ -84,17 +84,40 @@ __device__ inline void stage_inputs(uint16_t* X, const Net& net, const float (&g
     for (int q = 0; q < KIN / 8; ++q) row[q] = uint4{w[4 * q], w[4 * q + 1], w[4 * q + 2], w[4 * q + 3]};
 }
 
+// The first layer's GELU in the FP8 form: its inputs carry a factor 16
+// (W1, b1 scaled), so the constants are scaled by 16^-3 and 16^-1 and the
+// result is 16 gelu(a), the hidden layer's scaled input; the roundings are
+// those of gelu_fast on the unscaled value.
+__device__ inline float gelu16(float a16)
+{
+    constexpr float K1 = GELU_K1 / (FP8_ACT_SCALE * FP8_ACT_SCALE * FP8_ACT_SCALE);
+    constexpr float K2 = GELU_K2 / FP8_ACT_SCALE;
+    const float y2 = a16 * __builtin_fmaf(K1, a16 * a16, K2);
+    return a16 * __builtin_amdgcn_rcpf(1.0f + __builtin_amdgcn_exp2f(y2));
+}
+// The second layer's GELU with run-time constants (FP8 form: inputs scaled
+// by 2^(aw + 4), result gelu(a) 2^(aw + 4)).
+__device__ inline float gelu_k(float a, float k1, float k2)
+{
+    const float y2 = a * __builtin_fmaf(k1, a * a, k2);
+    return a * __builtin_amdgcn_rcpf(1.0f + __builtin_amdgcn_exp2f(y2));
+}
+
 // Network outputs of the wavefront's 64 sites. X holds the staged inputs
 // (row per site); on return the area holds the standardised outputs as
 // FP32, out[site * LDO + o] for o < 37. Every lane must call it. The output
 // rows are longer than the input rows, so the upper half of the sites goes
-// first: its outputs then cover only its own, consumed, inputs.
+// first: its outputs then cover only its own, consumed, inputs. FP8: the
+// hidden layer in e4m3 (see Net).
+template <bool FP8>
 __device__ inline void network_outputs(const Net& net, uint16_t* X)
 {
     const int lane = lane_id(), col = lane & 15, quad = lane >> 4;
-    const float* b1 = net.params + OFF_B1;
-    const float* b2 = net.params + OFF_B2;
+    const float* b1 = FP8 ? net.b1s : net.params + OFF_B1;
+    const float* b2 = FP8 ? net.b2s : net.params + OFF_B2;
     const float* b3 = net.params + OFF_B3;
+    const uint16_t* W1 = FP8 ? net.W1s : net.W1b;
+    const uint16_t* W3 = FP8 ? net.W3s : net.W3p;
     wave_sync();
 
 #pragma unroll 1
@@ -116,27 +139,54 @@ __device__ inline void network_outputs(const Net& net, uint16_t* X)
                 const bf16x8 x0 = frag_im(Xh, LDX, 0, ks * 32), x1 = frag_im(Xh, LDX, 16, ks * 32);
 #pragma unroll
                 for (int mt = 0; mt < 8; ++mt) {
-                    const bf16x8 a = frag_im(net.W1b, net.ld1, mt * 16, ks * 32);
+                    const bf16x8 a = frag_im(W1, net.ld1, mt * 16, ks * 32);
                     acc[mt][0] = mfma(a, x0, ks == 0 ? bias[mt] : acc[mt][0]);
                     acc[mt][1] = mfma(a, x1, ks == 0 ? bias[mt] : acc[mt][1]);
                 }
             }
         }
         __builtin_amdgcn_sched_barrier(0);
-        // GELU, BF16 into the B fragments of the next layer
         bf16x8 hb[4][2];
+        if constexpr (FP8) {
+            // GELU, e4m3 into the B fragments of the hidden layer
+            uint64_t hq[4][2];
 #pragma unroll
-        for (int kb = 0; kb < 4; ++kb)
+            for (int kb = 0; kb < 4; ++kb)
 #pragma unroll
-            for (int nt = 0; nt < 2; ++nt)
-#pragma unroll
-                for (int j = 0; j < 4; ++j) {
-                    hb[kb][nt][j] = to_bf16(gelu_fast(acc[2 * kb][nt][j]));
-                    hb[kb][nt][4 + j] = to_bf16(gelu_fast(acc[2 * kb + 1][nt][j]));
+                for (int nt = 0; nt < 2; ++nt) {
+                    const f32x4 lo4 = acc[2 * kb][nt], hi4 = acc[2 * kb + 1][nt];
+                    uint32_t lo = pack_fp8<false>(gelu16(lo4[0]), gelu16(lo4[1]), 0u);
+                    lo = pack_fp8<true>(gelu16(lo4[2]), gelu16(lo4[3]), lo);
+                    uint32_t hi = pack_fp8<false>(gelu16(hi4[0]), gelu16(hi4[1]), 0u);
+                    hi = pack_fp8<true>(gelu16(hi4[2]), gelu16(hi4[3]), hi);
+                    hq[kb][nt] = (uint64_t)lo | ((uint64_t)hi << 32);
                 }
-
-        // layer 2: H2^T = W2 H1^T + b2 (weight columns in chained order)
-        {
+            // layer 2 on e4m3 operands: H2^T 2^(aw + 4) = W2q H1q^T + b2s
+            f32x4 bias[8];
+#pragma unroll
+            for (int mt = 0; mt < 8; ++mt) bias[mt] = bias4(b2 + 16 * mt + 4 * quad);
+#pragma unroll
+            for (int kb = 0; kb < 4; ++kb) {
+                __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+                for (int mt = 0; mt < 8; ++mt) {
+                    const uint64_t a = frag8_im(net.W2q, net.ldq, mt * 16, kb * 32);
+                    acc[mt][0] = mfma_fp8(a, hq[kb][0], kb == 0 ? bias[mt] : acc[mt][0]);
+                    acc[mt][1] = mfma_fp8(a, hq[kb][1], kb == 0 ? bias[mt] : acc[mt][1]);
+                }
+            }
+        } else {
+            // GELU, BF16 into the B fragments of the next layer
+#pragma unroll
+            for (int kb = 0; kb < 4; ++kb)
+#pragma unroll
+                for (int nt = 0; nt < 2; ++nt)
+#pragma unroll
+                    for (int j = 0; j < 4; ++j) {
+                        hb[kb][nt][j] = to_bf16(gelu_fast(acc[2 * kb][nt][j]));
+                        hb[kb][nt][4 + j] = to_bf16(gelu_fast(acc[2 * kb + 1][nt][j]));
+                    }
+            // layer 2: H2^T = W2 H1^T + b2 (weight columns in chained order)
             f32x4 bias[8];
 #pragma unroll
             for (int mt = 0; mt < 8; ++mt) bias[mt] = bias4(b2 + 16 * mt + 4 * quad);
@@ -152,14 +202,19 @@ __device__ inline void network_outputs(const Net& net, uint16_t* X)
             }
         }
         __builtin_amdgcn_sched_barrier(0);
+        float k1 = GELU_K1, k2 = GELU_K2;
+        if constexpr (FP8) {
+            k1 = net.gk2[0];
+            k2 = net.gk2[1];
+        }
 #pragma unroll
         for (int kb = 0; kb < 4; ++kb)
 #pragma unroll
             for (int nt = 0; nt < 2; ++nt)
 #pragma unroll
                 for (int j = 0; j < 4; ++j) {
-                    hb[kb][nt][j] = to_bf16(gelu_fast(acc[2 * kb][nt][j]));
-                    hb[kb][nt][4 + j] = to_bf16(gelu_fast(acc[2 * kb + 1][nt][j]));
+                    hb[kb][nt][j] = to_bf16(gelu_k(acc[2 * kb][nt][j], k1, k2));
+                    hb[kb][nt][4 + j] = to_bf16(gelu_k(acc[2 * kb + 1][nt][j], k1, k2));
                 }
 
         // layer 3: O^T (48 x 32) = W3 H2^T + b3 (outputs 37..47 zero)
@@ -178,7 +233,7 @@ __device__ inline void network_outputs(const Net& net, uint16_t* X)
                 __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
                 for (int mt = 0; mt < 3; ++mt) {
-                    const bf16x8 a = frag_im(net.W3p, net.ld23, mt * 16, kb * 32);
+                    const bf16x8 a = frag_im(W3, net.ld23, mt * 16, kb * 32);
                     acc3[mt][0] = mfma(a, hb[kb][0], kb == 0 ? bias[mt] : acc3[mt][0]);
                     acc3[mt][1] = mfma(a, hb[kb][1], kb == 0 ? bias[mt] : acc3[mt][1]);
                 }
@@ -203,37 +258,58 @@ __device__ inline void network_outputs(const Net& net, uint16_t* X)
 }
 
 // LDS copy of the inference weights, rows padded by 16 bytes so that the 16
-// rows of a fragment fall on different banks.
+// rows of a fragment fall on different banks. The FP8 form keeps its e4m3
+// W2 (rows of HID + 8 bytes, copied 8 bytes at a time) in the W2 area.
 constexpr int LDW1 = KIN + 8;
 constexpr int LDW23 = HID + 8;
+constexpr int LDWQ = HID + 8;
 struct SharedWeights {
     uint16_t W1[HID * LDW1];
     uint16_t W2[HID * LDW23];
     uint16_t W3[NOUT * LDW23];
 };
+static_assert(HID * LDWQ <= HID * LDW23 * 2, "the e4m3 W2 copy fits the W2 area");
 
-// Copy the BF16 inference weights of `net` into LDS (all threads of the
-// workgroup; the caller synchronises) and return the view that reads them.
-template <int NTHREADS>
+// Copy the inference weights of `net` (BF16, or the FP8 form's) into LDS
+// (all threads of the workgroup; the caller synchronises) and return the
+// view that reads them.
+template <int NTHREADS, bool FP8>
 __device__ inline Net share_weights(const Net& net, SharedWeights& S)
 {
     const int tid = threadIdx.x;
+    const uint16_t* W1 = FP8 ? net.W1s : net.W1b;
+    const uint16_t* W3 = FP8 ? net.W3s : net.W3p;
     for (int i = tid; i < HID * KIN / 8; i += NTHREADS) {
         const int r = i / (KIN / 8), c = (i % (KIN / 8)) * 8;
-        *(uint4*)(S.W1 + r * LDW1 + c) = *(const uint4*)(net.W1b + r * KIN + c);
+        *(uint4*)(S.W1 + r * LDW1 + c) = *(const uint4*)(W1 + r * KIN + c);
     }
-    for (int i = tid; i < HID * HID / 8; i += NTHREADS) {
-        const int r = i / (HID / 8), c = (i % (HID / 8)) * 8;
-        *(uint4*)(S.W2 + r * LDW23 + c) = *(const uint4*)(net.W2p + r * HID + c);
+    if constexpr (FP8) {
+        uint8_t* W2q = (uint8_t*)S.W2;
+        for (int i = tid; i < HID * HID / 8; i += NTHREADS) {
+            const int r = i / (HID / 8), c = (i % (HID / 8)) * 8;
+            *(uint2*)(W2q + r * LDWQ + c) = *(const uint2*)(net.W2q + r * HID + c);
+        }
+    } else {
+        for (int i = tid; i < HID * HID / 8; i += NTHREADS) {
+            const int r = i / (HID / 8), c = (i % (HID / 8)) * 8;
+            *(uint4*)(S.W2 + r * LDW23 + c) = *(const uint4*)(net.W2p + r * HID + c);
+        }
     }
     for (int i = tid; i < NOUT * HID / 8; i += NTHREADS) {
         const int r = i / (HID / 8), c = (i % (HID / 8)) * 8;
-        *(uint4*)(S.W3 + r * LDW23 + c) = *(const uint4*)(net.W3p + r * HID + c);
+        *(uint4*)(S.W3 + r * LDW23 + c) = *(const uint4*)(W3 + r * HID + c);
     }
     Net v = net;
-    v.W1b = S.W1;
-    v.W2p = S.W2;
-    v.W3p = S.W3;
+    if constexpr (FP8) {
+        v.W1s = S.W1;
+        v.W2q = (const uint8_t*)S.W2;
+        v.W3s = S.W3;
+        v.ldq = LDWQ;
+    } else {
+        v.W1b = S.W1;
+        v.W2p = S.W2;
+        v.W3p = S.W3;
+    }
     v.ld1 = LDW1;
     v.ld23 = LDW23;
     return v;

@@ -95,6 +95,8 @@ _SIGNATURES = {
                                     _VP]),
     "lb_mlp_equilibrium": (ctypes.c_int, [_VP, _VP, _I64, ctypes.c_float, _VP, _VP, _VP]),
     "lb_pairgen": (ctypes.c_int, [_VP, _VP, _I64, ctypes.c_uint64, _D, _VP]),
+    "lb_mlp_set_precision": (ctypes.c_int, [_VP, _I32]),
+    "lb_mlp_get_precision": (ctypes.c_int, [_VP]),
     "lb_set_surrogate": (ctypes.c_int, [_VP, _VP, _D]),
     "lb_surrogate_counts": (ctypes.c_int, [_VP, _VP]),
 }
@@ -271,6 +273,17 @@ class Mlp:
 
     def init(self, seed: int):
         _mcheck(lib().lb_mlp_init(self.handle, seed), self.handle, "lb_mlp_init")
+
+    MLP_PRECISIONS = {"bf16": 0, "fp8": 1}
+
+    def set_precision(self, precision: str):
+        """Inference precision: "bf16", or "fp8" (the hidden layer in e4m3)."""
+        _mcheck(lib().lb_mlp_set_precision(self.handle, self.MLP_PRECISIONS[precision]), self.handle,
+                "lb_mlp_set_precision")
+
+    def get_precision(self) -> str:
+        code = lib().lb_mlp_get_precision(self.handle)
+        return {v: k for k, v in self.MLP_PRECISIONS.items()}[code]
 
     def set_params(self, theta):
         a = np.ascontiguousarray(theta, dtype=np.float32)

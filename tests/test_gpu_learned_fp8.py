@@ -1,0 +1,195 @@
+"""GPU parity of the learned collide's FP8 form (the hidden 128 x 128 layer
+in e4m3 on the FP8 matrix instructions; first and last layers BF16)
+against the oracle's FP8 forward pass (oracle/surrogate.py, fp8=True).
+
+Tolerance, per site in units of w_p (divided by tau for a step):
+  2 B1 + 8 B2, with B1 = surrogate.fp8_flip_bound (one e4m3 flip of one
+  hidden-layer input, to first order) and B2 = surrogate.flip_bound of the
+  FP8 forward (one BF16 flip of one second-layer activation). Both sides
+  round the same values at the same points (e4m3 for the hidden layer's
+  inputs and weights, BF16 elsewhere) and differ before rounding only by
+  FP32 against FP64 arithmetic, so flips are rare: the median site agrees to
+  FP32 arithmetic (<= 1e-6), which also catches a wrongly scaled or packed
+  e4m3 weight (it would move every site).
+"""
+import numpy as np
+import pytest
+
+from oracle import lbm, surrogate as S
+from oracle.lattice import constants
+from paper_1804_01918_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+from paper_1804_01918_amd import lb  # noqa: E402
+
+TAU = 0.8
+FLOOR = 1e-6
+
+
+def _f32(a):
+    return np.ascontiguousarray(a, dtype=np.float32).astype(np.float64)
+
+
+def _dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float32)).cuda()
+
+
+def _bar(theta, nf, g):
+    return 2.0 * S.fp8_flip_bound(theta, nf, g) + 8.0 * S.flip_bound(theta, nf, g, fp8=True)
+
+
+def _check_sites(err, bar, floor, what):
+    err = np.asarray(err, dtype=np.float64)
+    bar = np.broadcast_to(np.asarray(bar, dtype=np.float64), err.shape)
+    worst = int(np.argmax(err / bar))
+    print(f"{what} sites={err.size} max={err.max():.3e} worst/bar={err[worst] / bar[worst]:.3f} "
+          f"bar range=[{bar.min():.2e}, {bar.max():.2e}] median={np.median(err):.3e}", flush=True)
+    assert np.all(err <= bar), (err[worst], bar[worst])
+    assert np.median(err) <= floor, (np.median(err), floor)
+
+
+@pytest.fixture(scope="module")
+def oracle_net():
+    pre, post = S.make_pairs(4096, seed=21, tau=TAU)
+    pre, post = _f32(pre), _f32(post)
+    norm = S.fit_normalization(pre, post, TAU)
+    theta, _ = S.train(pre, post, TAU, S.init_params(4), norm, batch=256, epochs=6, lr0=3e-3, seed=8)
+    return _f32(theta), _f32(norm)
+
+
+def _gpu_net(theta, norm, precision="fp8"):
+    m = lb.Mlp(8192)
+    m.set_params(theta)
+    m.set_normalization(norm)
+    m.set_precision(precision)
+    return m
+
+
+def test_precision_switch_and_rejection(oracle_net):
+    theta, norm = oracle_net
+    m = _gpu_net(theta, norm)
+    assert m.get_precision() == "fp8"
+    with pytest.raises(lb.LBError) as e:
+        lb._mcheck(lb.lib().lb_mlp_set_precision(m.handle, 7), m.handle, "set_precision")
+    assert e.value.code == lb.LB_EINVAL
+    m.set_precision("bf16")
+    assert m.get_precision() == "bf16"
+    m.close()
+
+
+def test_fp8_equilibrium_matches_oracle(consts, oracle_net):
+    theta, norm = oracle_net
+    m = _gpu_net(theta, norm)
+    nf = m.get_normalization().astype(np.float64)
+    pre, _ = S.make_pairs(2048, seed=31, tau=TAU)
+    pre = _f32(pre)
+    gh, res, fb = m.equilibrium(_dev(pre), 1e9)
+    gh = gh.cpu().numpy()
+    w = consts["w"]
+    rho, ux, uy, T = S.macro(pre)
+    box = S.in_box(rho, ux, uy, T)
+    want = S.surrogate_equilibrium(pre, theta, nf, emulate=True, fp8=True)
+    assert np.all(np.isfinite(want[box]))
+    assert np.array_equal(fb.cpu().numpy().astype(bool), ~box)
+    exact = lbm.init(rho[:, None], ux[:, None], uy[:, None], T[:, None])[:, :, 0].T - w
+    want = np.where(box[:, None], want, exact)
+    _check_sites(np.max(np.abs(gh - want) / w, axis=1), _bar(theta, nf, pre), FLOOR, "fp8 equilibrium")
+    # conserved moments exact to FP32 rounding, as in the BF16 form
+    for phi in S._basis():
+        scale = np.abs(pre * phi).sum(1) + 1e-3
+        assert np.max(np.abs(gh @ phi - pre @ phi) / scale) < 1e-5
+    # the FP8 form is in use: it differs from the BF16 form by far more than
+    # the parity bar at most sites
+    want16 = S.surrogate_equilibrium(pre, theta, nf, emulate=True)
+    d16 = np.max(np.abs(gh - want16) / w, axis=1)[box]
+    assert np.median(d16) > 100 * FLOOR
+    m.close()
+
+
+def test_fp8_copies_follow_new_parameters(consts, oracle_net):
+    """Parameters set while the FP8 form is selected are packed again."""
+    theta, norm = oracle_net
+    m = _gpu_net(theta, norm)
+    theta2 = _f32(S.init_params(9))
+    m.set_params(theta2)
+    nf = m.get_normalization().astype(np.float64)
+    pre, _ = S.make_pairs(512, seed=32, tau=TAU)
+    pre = _f32(pre)
+    gh, _, _ = m.equilibrium(_dev(pre), 1e9)
+    gh = gh.cpu().numpy()
+    w = consts["w"]
+    rho, ux, uy, T = S.macro(pre)
+    box = S.in_box(rho, ux, uy, T)
+    want = S.surrogate_equilibrium(pre, theta2, nf, emulate=True, fp8=True)
+    err = np.max(np.abs(gh - want) / w, axis=1)[box]
+    _check_sites(err, _bar(theta2, nf, pre)[box], FLOOR, "fp8 after set_params")
+    m.close()
+
+
+def _window_step(fields, site, collide):
+    rho, ux, uy, T = fields
+    lx, ly = rho.shape
+    x0, y0 = site
+    xs, ys = (x0 + np.arange(-3, 4)) % lx, (y0 + np.arange(-3, 4)) % ly
+    ix = np.ix_(xs, ys)
+    win = lbm.init(rho[ix], ux[ix], uy[ix], T[ix])
+    w = constants()["w"][:, None, None]
+    win = w + _f32(win - w)
+    c = constants()["c"]
+    pulled = np.empty((37, 1, 1))
+    for p, (cx, cy) in enumerate(c):
+        pulled[p, 0, 0] = win[p, 3 - cx, 3 - cy]
+    return collide(pulled)[:, 0, 0]
+
+
+@pytest.mark.parametrize("L,kind,layout", [(128, "rayleigh_taylor", "caosoa"), (96, "shear_wave", "soa"),
+                                           (2048, "shear_wave", "caosoa")])
+def test_fp8_learned_step_matches_oracle(consts, oracle_net, L, kind, layout):
+    """One FP8 learned step (no fallback) against the oracle's FP8 learned
+    collide at sampled sites (corners, edges, tile seams, random)."""
+    theta, norm = oracle_net
+    m = _gpu_net(theta, norm)
+    nf = m.get_normalization().astype(np.float64)
+    lx = ly = L
+    fields = inputs.make_state(kind, lx, ly, seed=2)
+    rng = np.random.default_rng(6)
+    sites = sorted({(0, 0), (lx - 1, ly - 1), (0, ly - 1), (lx // 2, min(511, ly - 1)), (3, ly // 2)} |
+                   {(int(x), int(y)) for x, y in rng.integers(0, L, size=(10, 2))})
+    with lb.Lattice(lx, ly, TAU, [torch.from_numpy(a).cuda() for a in fields], precision="f32s",
+                    layout=layout) as lat:
+        lat.set_surrogate(m, 1e9)
+        lat.step(1)
+        f = lat.get_populations()
+        got = torch.stack([f[:, x, y] for x, y in sites]).cpu().numpy()
+        nfb, ntot = lat.surrogate_counts()
+    assert (nfb, ntot) == (0, lx * ly)
+    w = consts["w"]
+
+    def collide(win):
+        g = _f32(win.reshape(37, -1).T - w)
+        out, fb, _ = S.surrogate_collide(g, TAU, theta, nf, 1e9, fp8=True)
+        assert not fb.any()
+        return (out + w).T.reshape(win.shape)
+
+    ref = np.stack([_window_step(fields, s, collide) for s in sites])
+    pulled = np.stack([_window_step(fields, s, lambda win: win) for s in sites]) - w
+    _check_sites(np.max(np.abs(got - ref) / w, axis=1), _bar(theta, nf, pulled) / TAU, FLOOR / TAU,
+                 f"fp8 step {L} {kind} {layout}")
+    m.close()
+
+
+def test_fp8_threshold_zero_is_the_plain_step(oracle_net):
+    """Every site falls back: the FP8 kernels' step equals the plain FP32
+    step bit for bit."""
+    theta, norm = oracle_net
+    m = _gpu_net(theta, norm)
+    fields = inputs.rayleigh_taylor(64, 256, seed=3)
+    with lb.Lattice(64, 256, TAU, fields, precision="f32s", layout="caosoa") as a, \
+            lb.Lattice(64, 256, TAU, fields, precision="f32s", layout="caosoa") as b:
+        a.set_surrogate(m, 0.0)
+        a.step(3)
+        b.step(3)
+        assert torch.equal(a.raw_state(), b.raw_state())
+    m.close()
