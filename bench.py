@@ -211,6 +211,23 @@ def learned_variant(args, torch, lb, inputs, run, counts, nsites, shear_ref, rt_
         v["rayleigh_taylor_2048"] = {"error_vs_f64_after_steps": ERR_STEPS_2048,
                                      "fallback_fraction": counts.get("fallback_fraction"),
                                      "field_error_vs_f64": field_errors(rt_ref, mom)}
+    # the same trained network with its hidden layer in FP8 (e4m3)
+    net.set_precision("fp8")
+    counts.clear()
+    dt, mom = run("f32s", "caosoa", timed, args.warmup, keep=True, net=net)
+    m8 = nsites * timed / dt / 1e6
+    v8 = {"mlups": m8, "ms_per_step": dt / timed * 1e3, "threshold": THRESHOLD,
+          "hidden_layer": "e4m3 inputs and weights, v_mfma_f32_16x16x32_fp8_fp8; first and last layers BF16",
+          "fallback_fraction": counts.get("fallback_fraction"), "error_vs_f64_after_steps": ERR_STEPS_2048,
+          "field_error_vs_f64": field_errors(shear_ref, mom) if shear_ref is not None else None}
+    if rt_ref is not None:
+        counts.clear()
+        _, mom = run("f32s", "caosoa", timed, args.warmup, keep=True, state=rt, net=net)
+        v8["rayleigh_taylor_2048"] = {"error_vs_f64_after_steps": ERR_STEPS_2048,
+                                      "fallback_fraction": counts.get("fallback_fraction"),
+                                      "field_error_vs_f64": field_errors(rt_ref, mom)}
+    net.set_precision("bf16")
+    v["fp8_hidden_layer"] = v8
     return v, net
 
 
@@ -407,7 +424,8 @@ def main():
     ap.add_argument("--scale-steps", type=int, default=ERR_STEPS_8192,
                     help="total steps (warm-up included) of the 8192 x 8192 runs")
     ap.add_argument("--only", default=None,
-                    help="precision:layout[:split][:walls], or 'learned', to time alone")
+                    help="precision:layout[:split][:walls], 'learned' or 'learned_fp8', to time alone")
+    ap.add_argument("--lattice", type=int, default=LX, help="with --only precision:layout: the lattice size N x N")
     ap.add_argument("--copy-bytes", type=int, default=0,
                     help="only run the library's copy kernel on buffers of this size (counter calibration)")
     ap.add_argument("--copy-reps", type=int, default=5)
@@ -453,8 +471,10 @@ def main():
         torch.cuda.empty_cache()
         return dt, mom
 
-    if args.only == "learned":
+    if args.only in ("learned", "learned_fp8"):
         net, _ = train_network(torch, lb, train=not args.untrained)
+        if args.only == "learned_fp8":
+            net.set_precision("fp8")
         dt, _ = run("f32s", "caosoa", args.steps, args.warmup, net=net,
                     threshold=THRESHOLD if args.threshold is None else args.threshold)
         print(json.dumps({"only": args.only, "mlups": nsites * args.steps / dt / 1e6,
@@ -463,13 +483,17 @@ def main():
         return
     if args.only:
         # precision:layout[:split][:walls]; "walls" runs the Rayleigh-Taylor-like
-        # state under gravity between the diffuse walls
+        # state under gravity between the diffuse walls; --lattice N times an
+        # N x N lattice (the Rayleigh-Taylor-like state unless N is 2048)
         parts = args.only.split(":")
         walls = "walls" in parts[2:]
-        state = (LX, LY, [torch.from_numpy(a).cuda() for a in inputs.rayleigh_taylor(LX, LY, seed=0)]) if walls else None
+        n = args.lattice
+        state = None
+        if walls or n != LX:
+            state = (n, n, [torch.from_numpy(a).cuda() for a in inputs.rayleigh_taylor(n, n, seed=0)])
         dt, _ = run(parts[0], parts[1], args.steps, args.warmup, split="split" in parts[2:], state=state,
                     bc=dict(force=RT_GRAVITY, **RT_WALLS) if walls else None)
-        print(json.dumps({"only": args.only, "mlups": nsites * args.steps / dt / 1e6,
+        print(json.dumps({"only": args.only, "lattice": [n, n], "mlups": n * n * args.steps / dt / 1e6,
                           "ms_per_step": dt / args.steps * 1e3}))
         return
 
