@@ -327,6 +327,8 @@ int lb_mlp_train(lb_mlp *m, const float *pre, const float *post, int64_t n, doub
  * a lower-precision variant of the learned collide.) */
 enum { LB_MLP_BF16 = 0, LB_MLP_FP8 = 1 };
 int lb_mlp_set_precision(lb_mlp *m, int32_t precision);
+/* The network's inference precision (LB_MLP_BF16 or LB_MLP_FP8), or
+ * LB_EINVAL for a NULL network. Host only. */
 int lb_mlp_get_precision(const lb_mlp *m);
 
 /* Learned equilibrium g_hat of n device sites pre[n][37] (plain equilibrium
