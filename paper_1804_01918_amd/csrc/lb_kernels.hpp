@@ -432,25 +432,17 @@ __global__ __launch_bounds__(BLOCK) void k_set(typename P::T* __restrict__ buf, 
     }
 }
 
-// Streaming copy of 16-byte words (the achievable-bandwidth reference):
-// each thread moves COPY_UNROLL words, all loads issued before the stores.
-constexpr int COPY_UNROLL = 4;
+// Streaming copy of 16-byte words (the achievable-bandwidth reference): one
+// word per thread, streaming hints on both sides. Of the forms measured on
+// this GPU (1, 2 or 4 words per thread, 256 to 1024 threads per workgroup,
+// grid-stride loops, with or without the hints) this one moves the most.
+constexpr int COPY_UNROLL = 1;
 typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
 __global__ __launch_bounds__(BLOCK) void k_copy16(const u32x4* __restrict__ src, u32x4* __restrict__ dst,
                                                   int64_t n16)
 {
-    const int64_t base = (int64_t)blockIdx.x * BLOCK * COPY_UNROLL + threadIdx.x;
-    u32x4 v[COPY_UNROLL];
-#pragma unroll
-    for (int k = 0; k < COPY_UNROLL; ++k) {
-        const int64_t i = base + (int64_t)k * BLOCK;
-        if (i < n16) v[k] = ld_stream(src + i);
-    }
-#pragma unroll
-    for (int k = 0; k < COPY_UNROLL; ++k) {
-        const int64_t i = base + (int64_t)k * BLOCK;
-        if (i < n16) st_stream(dst + i, v[k]);
-    }
+    const int64_t i = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
+    if (i < n16) st_stream(dst + i, ld_stream(src + i));
 }
 
 }  // namespace d2q37

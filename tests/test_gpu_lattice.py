@@ -295,3 +295,16 @@ def test_misaligned_buffer_rejected():
     rc = lb.lib().lb_init(ctypes.byref(ctx), ctypes.byref(cfg), *[a.data_ptr() for a in lat._fields_keepalive])
     assert rc == lb.LB_EINVAL
     lat.close()
+
+
+@pytest.mark.parametrize("nbytes", [16, 4096 + 16, (1 << 20) + 48, 3 * 256 * 16 + 16])
+def test_copy_kernel_bytes(nbytes):
+    """The bandwidth-reference copy moves exactly the given bytes (one 16-byte
+    word per thread, ragged last workgroup) and nothing past them."""
+    g = torch.Generator().manual_seed(nbytes)
+    src = torch.randint(0, 256, (nbytes,), dtype=torch.uint8, generator=g).cuda()
+    dst = torch.full((nbytes + 256,), 0xA5, dtype=torch.uint8, device="cuda")
+    lb.device_copy(dst[:nbytes], src)
+    torch.cuda.synchronize()
+    assert torch.equal(dst[:nbytes], src)
+    assert bool((dst[nbytes:] == 0xA5).all())
