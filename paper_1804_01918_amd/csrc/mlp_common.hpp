@@ -166,6 +166,11 @@ struct Net {
     const float* b2s = nullptr;
     const float* gk2 = nullptr;
     int ldq = HID;        // row stride of W2q in bytes
+    // LDS copies of the biases of the form in use (set by share_weights;
+    // null: read them from params, or b1s / b2s in the FP8 form)
+    const float* lb1 = nullptr;
+    const float* lb2 = nullptr;
+    const float* lb3 = nullptr;
 };
 
 // ---- conserved part and residual of shifted populations -----------------------

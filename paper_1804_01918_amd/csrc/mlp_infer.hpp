@@ -17,6 +17,8 @@
 // site's 37 outputs to its lane) pass through a per-wavefront LDS area.
 #pragma once
 
+#include <type_traits>
+
 #include "mlp_common.hpp"
 
 namespace d2q37 {
@@ -109,134 +111,156 @@ __device__ inline float gelu_k(float a, float k1, float k2)
 // rows are longer than the input rows, so the upper half of the sites goes
 // first: its outputs then cover only its own, consumed, inputs. FP8: the
 // hidden layer in e4m3 (see Net).
+//
+// Each of the first two layers runs as a pipeline over its eight 16-unit
+// tiles: step s reads tile s + 1's weight fragments and bias from LDS,
+// multiplies tile s on the matrix core, and evaluates the GELUs of tile
+// s - 1, so the LDS and matrix-core latencies of one tile are covered by
+// the vector work of another. The last layer takes the hidden layer's
+// activations 32 units at a time, as they are produced. Every accumulation
+// runs in the same order as a layer-at-a-time evaluation (bias first, then
+// k blocks in increasing order), so the results do not depend on this
+// schedule.
 template <bool FP8>
 __device__ inline void network_outputs(const Net& net, uint16_t* X)
 {
     const int lane = lane_id(), col = lane & 15, quad = lane >> 4;
-    const float* b1 = FP8 ? net.b1s : net.params + OFF_B1;
-    const float* b2 = FP8 ? net.b2s : net.params + OFF_B2;
-    const float* b3 = net.params + OFF_B3;
+    const float* b1 = net.lb1 ? net.lb1 : FP8 ? net.b1s : net.params + OFF_B1;
+    const float* b2 = net.lb2 ? net.lb2 : FP8 ? net.b2s : net.params + OFF_B2;
+    const float* b3 = net.lb3 ? net.lb3 : net.params + OFF_B3;
     const uint16_t* W1 = FP8 ? net.W1s : net.W1b;
     const uint16_t* W3 = FP8 ? net.W3s : net.W3p;
+    float k1 = GELU_K1, k2 = GELU_K2;
+    if constexpr (FP8) {
+        k1 = net.gk2[0];
+        k2 = net.gk2[1];
+    }
+    typedef typename std::conditional<FP8, uint64_t, bf16x8>::type W2Frag;
     wave_sync();
 
 #pragma unroll 1
     for (int pass = 0; pass < 2; ++pass) {
         const int half = 1 - pass;
         const uint16_t* Xh = X + half * 32 * LDX;
+        bf16x8 xf[2][2];  // inputs: B fragments of both k steps, both site tiles
+#pragma unroll
+        for (int ks = 0; ks < 2; ++ks)
+#pragma unroll
+            for (int nt = 0; nt < 2; ++nt) xf[ks][nt] = frag_im(Xh, LDX, 16 * nt, ks * 32);
 
-        // Biases enter as the accumulator of each chain's first product: row
-        // 4 quad + j of tile mt is unit 16 mt + 4 quad + j.
-        // layer 1: H1^T (128 x 32) = W1 (128 x 64) X^T (64 x 32) + b1
-        f32x4 acc[8][2];
-        {
-            f32x4 bias[8];
-#pragma unroll
-            for (int mt = 0; mt < 8; ++mt) bias[mt] = bias4(b1 + 16 * mt + 4 * quad);
-#pragma unroll
-            for (int ks = 0; ks < 2; ++ks) {
-                __builtin_amdgcn_sched_barrier(0);  // one k block of weight fragments in flight
-                const bf16x8 x0 = frag_im(Xh, LDX, 0, ks * 32), x1 = frag_im(Xh, LDX, 16, ks * 32);
-#pragma unroll
-                for (int mt = 0; mt < 8; ++mt) {
-                    const bf16x8 a = frag_im(W1, net.ld1, mt * 16, ks * 32);
-                    acc[mt][0] = mfma(a, x0, ks == 0 ? bias[mt] : acc[mt][0]);
-                    acc[mt][1] = mfma(a, x1, ks == 0 ? bias[mt] : acc[mt][1]);
-                }
-            }
-        }
-        __builtin_amdgcn_sched_barrier(0);
+        // layer 1: tile mt of H1^T (16 units x 32 sites) = W1 X^T + b1 (row
+        // 4 quad + j of the tile is unit 16 mt + 4 quad + j); its GELUs fill
+        // slots 4 (mt & 1) + j of k block mt / 2 of the hidden layer's B
+        // fragments (FP8: e4m3 bytes, word mt & 1 of the 8-byte fragment)
         bf16x8 hb[4][2];
-        if constexpr (FP8) {
-            // GELU, e4m3 into the B fragments of the hidden layer
-            uint64_t hq[4][2];
+        uint32_t hq[4][2][2];
+        {
+            bf16x8 w[2][2];  // [tile & 1][k step]
+            f32x4 bias[2], a[2][2];
+            auto load = [&](int mt) {
 #pragma unroll
-            for (int kb = 0; kb < 4; ++kb)
+                for (int ks = 0; ks < 2; ++ks) w[mt & 1][ks] = frag_im(W1, net.ld1, mt * 16, ks * 32);
+                bias[mt & 1] = bias4(b1 + 16 * mt + 4 * quad);
+            };
+            auto mul = [&](int mt) {
+                const int b = mt & 1;
+                a[b][0] = a[b][1] = bias[b];
+#pragma unroll
+                for (int ks = 0; ks < 2; ++ks)
+#pragma unroll
+                    for (int nt = 0; nt < 2; ++nt) a[b][nt] = mfma(w[b][ks], xf[ks][nt], a[b][nt]);
+            };
+            // (the empty asm pins each tile's GELUs to their pipeline step:
+            // nothing else consumes them before the hidden layer)
+            auto act = [&](int mt) {
+                const int b = mt & 1;
 #pragma unroll
                 for (int nt = 0; nt < 2; ++nt) {
-                    const f32x4 lo4 = acc[2 * kb][nt], hi4 = acc[2 * kb + 1][nt];
-                    uint32_t lo = pack_fp8<false>(gelu16(lo4[0]), gelu16(lo4[1]), 0u);
-                    lo = pack_fp8<true>(gelu16(lo4[2]), gelu16(lo4[3]), lo);
-                    uint32_t hi = pack_fp8<false>(gelu16(hi4[0]), gelu16(hi4[1]), 0u);
-                    hi = pack_fp8<true>(gelu16(hi4[2]), gelu16(hi4[3]), hi);
-                    hq[kb][nt] = (uint64_t)lo | ((uint64_t)hi << 32);
+                    if constexpr (FP8) {
+                        const uint32_t v = pack_fp8<false>(gelu16(a[b][nt][0]), gelu16(a[b][nt][1]), 0u);
+                        hq[mt >> 1][nt][mt & 1] = pack_fp8<true>(gelu16(a[b][nt][2]), gelu16(a[b][nt][3]), v);
+                        asm volatile("" : "+v"(hq[mt >> 1][nt][mt & 1]));
+                    } else {
+#pragma unroll
+                        for (int j = 0; j < 4; ++j) hb[mt >> 1][nt][4 * (mt & 1) + j] = to_bf16(gelu_fast(a[b][nt][j]));
+                        asm volatile("" : "+v"(hb[mt >> 1][nt]));
+                    }
                 }
-            // layer 2 on e4m3 operands: H2^T 2^(aw + 4) = W2q H1q^T + b2s
-            f32x4 bias[8];
+            };
+            load(0);
+            __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
-            for (int mt = 0; mt < 8; ++mt) bias[mt] = bias4(b2 + 16 * mt + 4 * quad);
-#pragma unroll
-            for (int kb = 0; kb < 4; ++kb) {
+            for (int s = 0; s <= 8; ++s) {
+                if (s + 1 < 8) load(s + 1);
+                if (s < 8) mul(s);
+                if (s > 0) act(s - 1);
                 __builtin_amdgcn_sched_barrier(0);
-#pragma unroll
-                for (int mt = 0; mt < 8; ++mt) {
-                    const uint64_t a = frag8_im(net.W2q, net.ldq, mt * 16, kb * 32);
-                    acc[mt][0] = mfma_fp8(a, hq[kb][0], kb == 0 ? bias[mt] : acc[mt][0]);
-                    acc[mt][1] = mfma_fp8(a, hq[kb][1], kb == 0 ? bias[mt] : acc[mt][1]);
-                }
             }
-        } else {
-            // GELU, BF16 into the B fragments of the next layer
+        }
+
+        // hidden layer: tile mt of H2^T = W2 H1^T + b2 (weight columns in
+        // chained order; FP8: H2^T 2^(aw + 4) = W2q H1q^T + b2s); last layer
+        // O^T (48 x 32) = W3 H2^T + b3 (outputs 37..47 zero), its k block kb
+        // taken once hidden tiles 2 kb and 2 kb + 1 are activated
+        f32x4 acc3[3][2];
 #pragma unroll
-            for (int kb = 0; kb < 4; ++kb)
+        for (int m3 = 0; m3 < 3; ++m3)
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int o = 16 * m3 + 4 * quad + i;
+                acc3[m3][0][i] = acc3[m3][1][i] = o < Q ? b3[o < Q ? o : 0] : 0.0f;
+            }
+        {
+            W2Frag w[2][4];  // [tile & 1][k block]
+            bf16x8 w3[3], h2[2];
+            f32x4 bias[2], a[2][2];
+            auto load = [&](int mt) {
+#pragma unroll
+                for (int kb = 0; kb < 4; ++kb) {
+                    if constexpr (FP8) w[mt & 1][kb] = frag8_im(net.W2q, net.ldq, mt * 16, kb * 32);
+                    else w[mt & 1][kb] = frag_im(net.W2p, net.ld23, mt * 16, kb * 32);
+                }
+                bias[mt & 1] = bias4(b2 + 16 * mt + 4 * quad);
+            };
+            auto mul = [&](int mt) {
+                const int b = mt & 1;
+                a[b][0] = a[b][1] = bias[b];
+#pragma unroll
+                for (int kb = 0; kb < 4; ++kb)
+#pragma unroll
+                    for (int nt = 0; nt < 2; ++nt) {
+                        if constexpr (FP8)
+                            a[b][nt] = mfma_fp8(w[b][kb], (uint64_t)hq[kb][nt][0] | ((uint64_t)hq[kb][nt][1] << 32),
+                                                a[b][nt]);
+                        else
+                            a[b][nt] = mfma(w[b][kb], hb[kb][nt], a[b][nt]);
+                    }
+            };
+            auto act = [&](int mt) {
+                const int b = mt & 1;
 #pragma unroll
                 for (int nt = 0; nt < 2; ++nt)
 #pragma unroll
-                    for (int j = 0; j < 4; ++j) {
-                        hb[kb][nt][j] = to_bf16(gelu_fast(acc[2 * kb][nt][j]));
-                        hb[kb][nt][4 + j] = to_bf16(gelu_fast(acc[2 * kb + 1][nt][j]));
-                    }
-            // layer 2: H2^T = W2 H1^T + b2 (weight columns in chained order)
-            f32x4 bias[8];
+                    for (int j = 0; j < 4; ++j) h2[nt][4 * (mt & 1) + j] = to_bf16(gelu_k(a[b][nt][j], k1, k2));
+                if (mt & 1) {
 #pragma unroll
-            for (int mt = 0; mt < 8; ++mt) bias[mt] = bias4(b2 + 16 * mt + 4 * quad);
+                    for (int m3 = 0; m3 < 3; ++m3)
 #pragma unroll
-            for (int kb = 0; kb < 4; ++kb) {
+                        for (int nt = 0; nt < 2; ++nt) acc3[m3][nt] = mfma(w3[m3], h2[nt], acc3[m3][nt]);
+                }
+            };
+            load(0);
+            __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+            for (int s = 0; s <= 8; ++s) {
+                if (s + 1 < 8) load(s + 1);
+                if (s > 0 && ((s - 1) & 1)) {
+#pragma unroll
+                    for (int m3 = 0; m3 < 3; ++m3) w3[m3] = frag_im(W3, net.ld23, m3 * 16, ((s - 1) >> 1) * 32);
+                }
+                if (s < 8) mul(s);
+                if (s > 0) act(s - 1);
                 __builtin_amdgcn_sched_barrier(0);
-#pragma unroll
-                for (int mt = 0; mt < 8; ++mt) {
-                    const bf16x8 a = frag_im(net.W2p, net.ld23, mt * 16, kb * 32);
-                    acc[mt][0] = mfma(a, hb[kb][0], kb == 0 ? bias[mt] : acc[mt][0]);
-                    acc[mt][1] = mfma(a, hb[kb][1], kb == 0 ? bias[mt] : acc[mt][1]);
-                }
-            }
-        }
-        __builtin_amdgcn_sched_barrier(0);
-        float k1 = GELU_K1, k2 = GELU_K2;
-        if constexpr (FP8) {
-            k1 = net.gk2[0];
-            k2 = net.gk2[1];
-        }
-#pragma unroll
-        for (int kb = 0; kb < 4; ++kb)
-#pragma unroll
-            for (int nt = 0; nt < 2; ++nt)
-#pragma unroll
-                for (int j = 0; j < 4; ++j) {
-                    hb[kb][nt][j] = to_bf16(gelu_k(acc[2 * kb][nt][j], k1, k2));
-                    hb[kb][nt][4 + j] = to_bf16(gelu_k(acc[2 * kb + 1][nt][j], k1, k2));
-                }
-
-        // layer 3: O^T (48 x 32) = W3 H2^T + b3 (outputs 37..47 zero)
-        f32x4 acc3[3][2];
-        {
-            f32x4 bias[3];
-#pragma unroll
-            for (int mt = 0; mt < 3; ++mt)
-#pragma unroll
-                for (int i = 0; i < 4; ++i) {
-                    const int o = 16 * mt + 4 * quad + i;
-                    bias[mt][i] = o < Q ? b3[o < Q ? o : 0] : 0.0f;
-                }
-#pragma unroll
-            for (int kb = 0; kb < 4; ++kb) {
-                __builtin_amdgcn_sched_barrier(0);
-#pragma unroll
-                for (int mt = 0; mt < 3; ++mt) {
-                    const bf16x8 a = frag_im(W3, net.ld23, mt * 16, kb * 32);
-                    acc3[mt][0] = mfma(a, hb[kb][0], kb == 0 ? bias[mt] : acc3[mt][0]);
-                    acc3[mt][1] = mfma(a, hb[kb][1], kb == 0 ? bias[mt] : acc3[mt][1]);
-                }
             }
         }
         wave_sync();  // the half's input rows are dead before its outputs overwrite them
@@ -267,6 +291,9 @@ struct SharedWeights {
     uint16_t W1[HID * LDW1];
     uint16_t W2[HID * LDW23];
     uint16_t W3[NOUT * LDW23];
+    float b1[HID];   // biases of the form in use (FP8: the scaled b1s, b2s)
+    float b2[HID];
+    float b3[NOUT];  // zero past output 37
 };
 static_assert(HID * LDWQ <= HID * LDW23 * 2, "the e4m3 W2 copy fits the W2 area");
 
@@ -299,7 +326,17 @@ __device__ inline Net share_weights(const Net& net, SharedWeights& S)
         const int r = i / (HID / 8), c = (i % (HID / 8)) * 8;
         *(uint4*)(S.W3 + r * LDW23 + c) = *(const uint4*)(W3 + r * HID + c);
     }
+    const float* b1 = FP8 ? net.b1s : net.params + OFF_B1;
+    const float* b2 = FP8 ? net.b2s : net.params + OFF_B2;
+    for (int i = tid; i < HID; i += NTHREADS) {
+        S.b1[i] = b1[i];
+        S.b2[i] = b2[i];
+    }
+    for (int i = tid; i < NOUT; i += NTHREADS) S.b3[i] = i < Q ? net.params[OFF_B3 + i] : 0.0f;
     Net v = net;
+    v.lb1 = S.b1;
+    v.lb2 = S.b2;
+    v.lb3 = S.b3;
     if constexpr (FP8) {
         v.W1s = S.W1;
         v.W2q = (const uint8_t*)S.W2;
