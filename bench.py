@@ -195,6 +195,8 @@ def learned_variant(args, torch, lb, inputs, run, counts, nsites, shear_ref, rt_
     dt, mom = run("f32s", "caosoa", timed, args.warmup, keep=True, net=net)
     m = nsites * timed / dt / 1e6
     v = {"mlups": m, "ms_per_step": dt / timed * 1e3, "timed_steps": timed, "threshold": THRESHOLD,
+         "network_form": "first layer BF16 (v_mfma_f32_16x16x32_bf16); hidden activations, their GELU arithmetic "
+                         "and the last two layers binary16 (v_mfma_f32_16x16x32_f16); FP32 accumulation",
          "fallback_fraction": counts.get("fallback_fraction"),
          "mfma_tflops": m * 1e6 * MLP_FLOP_PER_SITE / 1e12,
          "mfma_frac": m * 1e6 * MLP_FLOP_PER_SITE / 1e12 / BF16_PEAK_TFLOPS,
@@ -226,7 +228,7 @@ def learned_variant(args, torch, lb, inputs, run, counts, nsites, shear_ref, rt_
         v8["rayleigh_taylor_2048"] = {"error_vs_f64_after_steps": ERR_STEPS_2048,
                                       "fallback_fraction": counts.get("fallback_fraction"),
                                       "field_error_vs_f64": field_errors(rt_ref, mom)}
-    net.set_precision("bf16")
+    net.set_precision("f16")
     v["fp8_hidden_layer"] = v8
     return v, net
 

@@ -239,8 +239,10 @@ int lb_copy(void *dst, const void *src, size_t bytes, void *stream);
  * from the moments in closed form; this option replaces that equilibrium by
  * a small network evaluated on the matrix cores:
  *   - input z = g / w_p (shifted populations of a site), standardised;
- *   - MLP 37 -> 128 -> 128 -> 37 with GELU (tanh form), BF16 operands and
- *     FP32 accumulation; its output y (de-standardised) is the part of the
+ *   - MLP 37 -> 128 -> 128 -> 37 with GELU (tanh form), FP32 accumulation,
+ *     operands in the precision lb_mlp_set_precision selects (BF16 first
+ *     layer, binary16 hidden layers by default); trained in BF16. Its
+ *     output y (de-standardised) is the part of the
  *     equilibrium that the conserved moments do not fix: g_hat = P(g) + d -
  *     P(d) with d = w_p y and P the orthogonal projection (1/w inner
  *     product) onto w * {1, xi_x, xi_y, xi^2 - 2}, so mass, momentum and
@@ -312,7 +314,11 @@ int lb_mlp_train(lb_mlp *m, const float *pre, const float *post, int64_t n, doub
 
 /* Precision of the network's inference (the learned collide and
  * lb_mlp_equilibrium; training is always BF16 with FP32 accumulation):
- *   LB_MLP_BF16  every layer BF16 x BF16 -> FP32 (the default);
+ *   LB_MLP_F16   the first layer BF16 x BF16 -> FP32; the hidden
+ *                activations in binary16 (IEEE half), their GELU evaluated
+ *                in binary16 arithmetic, one rounding to nearest even per
+ *                operation (see lb_mlp_gelu16); the last two layers
+ *                binary16 x binary16 -> FP32 (the default);
  *   LB_MLP_FP8   the hidden 128 x 128 layer in FP8 (e4m3, the OCP variant
  *                without infinities): its inputs, the first layer's GELU
  *                outputs, scaled by 16, and its weights, scaled by 2^aw
@@ -325,11 +331,22 @@ int lb_mlp_train(lb_mlp *m, const float *pre, const float *post, int64_t n, doub
  * (again after every lb_mlp_init, _set_params and _train while FP8 is set).
  * LB_EINVAL for a NULL network or an unknown precision. (Not in the paper:
  * a lower-precision variant of the learned collide.) */
-enum { LB_MLP_BF16 = 0, LB_MLP_FP8 = 1 };
+enum { LB_MLP_F16 = 0, LB_MLP_FP8 = 1 };
 int lb_mlp_set_precision(lb_mlp *m, int32_t precision);
-/* The network's inference precision (LB_MLP_BF16 or LB_MLP_FP8), or
+/* The network's inference precision (LB_MLP_F16 or LB_MLP_FP8), or
  * LB_EINVAL for a NULL network. Host only. */
 int lb_mlp_get_precision(const lb_mlp *m);
+
+/* The activation of the LB_MLP_F16 form on n device binary16 values x (bit
+ * patterns) into y: gelu(x) = x / (1 + 2^(x (K1 x^2 + K2))), with K1 =
+ * -2 log2(e) c A and K2 = -2 log2(e) c (c = sqrt(2 / pi), A = 0.044715: the
+ * tanh form of GELU) rounded to binary16, and every operation (the square,
+ * the fused K1 product and K2 sum, the product with x, the power of two,
+ * the sum with 1, the reciprocal, the last product) rounded to nearest even
+ * in binary16; the same instructions the learned collide runs. For
+ * checking the arithmetic against a host evaluation. Asynchronous on
+ * `stream`; LB_EINVAL for NULL pointers or n < 0. (Not in the paper.) */
+int lb_mlp_gelu16(const uint16_t *x, uint16_t *y, int64_t n, void *stream);
 
 /* Learned equilibrium g_hat of n device sites pre[n][37] (plain equilibrium
  * where the verdict is fallback); residual[n] (FP32) and fallback[n] (int32,

@@ -26,10 +26,17 @@ all its choices are readings stated here):
   u_y, rho (u_x^2 - u_y^2), rho u (|u|^2 + 4 T). A site falls back to the
   plain equilibrium if the residual exceeds the threshold or if (rho, |u|, T)
   leaves the training box [0.9, 1.1] x [0, 0.1] x [0.9, 1.1].
-* BF16 emulation mirrors the GPU: inputs and weights rounded to BF16, hidden
-  activations rounded to BF16 after GELU, sums in high precision; in the
-  backward pass the output gradient and the pre-activation gradients are
-  rounded to BF16 before the products, bias gradients use the unrounded ones.
+* BF16 emulation mirrors the GPU's training: inputs and weights rounded to
+  BF16, hidden activations rounded to BF16 after GELU, sums in high
+  precision; in the backward pass the output gradient and the
+  pre-activation gradients are rounded to BF16 before the products, bias
+  gradients use the unrounded ones.
+* Inference form (binary16 hidden layer, the GPU's default for the learned
+  collide): the inputs and W1 in BF16 as above; each pre-activation, taken
+  as the FP32 value the GPU accumulates, rounded to binary16 (IEEE half,
+  nearest even) and put through the GELU's tanh form evaluated in binary16
+  arithmetic, one rounding per operation (gelu_f16); W2 and W3 rounded to
+  binary16; sums in high precision.
 """
 from __future__ import annotations
 
@@ -158,6 +165,38 @@ def gelu(a):
     return a / (1.0 + np.exp(-2.0 * GELU_C * (a + GELU_A * a ** 3)))
 
 
+def f16(x) -> np.ndarray:
+    """Round to IEEE binary16 (11 significant bits, nearest with ties to
+    even, subnormals below 2^-14, beyond the largest finite value 65504:
+    infinity), returned as float64."""
+    with np.errstate(over="ignore"):
+        return np.asarray(x, dtype=np.float64).astype(np.float16).astype(np.float64)
+
+
+# The tanh form written as a / (1 + 2^(a (K1 a^2 + K2))): K1 = -2 log2(e) c A,
+# K2 = -2 log2(e) c, rounded to binary16 for the binary16 evaluation.
+LOG2E = 1.0 / math.log(2.0)
+GELU_K1_F16 = float(f16(-2.0 * LOG2E * GELU_C * GELU_A))
+GELU_K2_F16 = float(f16(-2.0 * LOG2E * GELU_C))
+
+
+def gelu_f16(a):
+    """GELU evaluated in binary16 arithmetic, every operation rounded to
+    nearest even: x = h(a); s = h(x^2); t = h(K1 s + K2) (one rounding for
+    the product and sum); y = h(x t); e = h(2^y); r = h(1 / h(e + 1));
+    result h(x r). The products and the sum of binary16 values are exact in
+    float64 before their one rounding, and 2^y and 1 / d are rounded
+    correctly from float64 (float64 error far below the binary16 spacing)."""
+    x = f16(a)
+    with np.errstate(over="ignore", invalid="ignore"):
+        s = f16(x * x)
+        t = f16(GELU_K1_F16 * s + GELU_K2_F16)
+        y = f16(x * t)
+        e = f16(np.exp2(y))
+        r = f16(1.0 / f16(e + 1.0))
+        return f16(x * r)
+
+
 def gelu_grad(a):
     s = 1.0 / (1.0 + np.exp(-2.0 * GELU_C * (a + GELU_A * a ** 3)))
     return s + a * s * (1.0 - s) * 2.0 * GELU_C * (1.0 + 3.0 * GELU_A * a * a)
@@ -196,14 +235,26 @@ def init_params(seed: int) -> np.ndarray:
     return theta
 
 
-def forward(theta, x_std, emulate=True, fp8=False):
-    """Network outputs (standardised) and the intermediates. fp8: the hidden
+def f32(v) -> np.ndarray:
+    return np.asarray(v, dtype=np.float64).astype(np.float32).astype(np.float64)
+
+
+def forward(theta, x_std, emulate=True, fp8=False, infer=False):
+    """Network outputs (standardised) and the intermediates. emulate: the
+    training form's BF16 roundings; with infer, the inference form's
+    binary16 hidden layer instead (see the module notes); fp8: the hidden
     layer's inputs and weights in e4m3 (FP8 form above), the rest in BF16
     (emulate must be set)."""
     p = unpack(theta)
     q = bf16 if emulate else (lambda v: v)
     x = q(x_std)
     a1 = x @ q(p["W1"]).T + p["b1"]
+    if emulate and infer and not fp8:
+        h1 = gelu_f16(f32(a1))
+        a2 = h1 @ f16(p["W2"]).T + p["b2"]
+        h2 = gelu_f16(f32(a2))
+        o = h2 @ f16(p["W3"]).T + p["b3"]
+        return o, (x, a1, h1, a2, h2)
     if fp8:
         sw = 2.0 ** fp8_weight_exponent(p["W2"])
         h1 = e4m3(gelu(a1) * FP8_ACT_SCALE) / FP8_ACT_SCALE
@@ -317,9 +368,11 @@ def train(pre, post, tau, theta0, norm, batch, epochs, lr0, seed, emulate=True, 
 # ---- the learned collide --------------------------------------------------------------
 
 def surrogate_equilibrium(g, theta, norm, emulate=True, fp8=False):
+    """Learned equilibrium of the sites g; with emulate, in the GPU's
+    inference form (binary16 hidden layer, or the FP8 form)."""
     w = constants()["w"]
     zs = (g / w - norm[0]) / norm[1]
-    o, _ = forward(theta, zs, emulate, fp8)
+    o, _ = forward(theta, zs, emulate, fp8, infer=True)
     d = w * (norm[2] + norm[3] * o)
     return conserved_part(g) + d - conserved_part(d)
 
@@ -357,11 +410,15 @@ def gelu_grad_max() -> float:
     return float(np.abs(gelu_grad(a)).max()) + 1e-6
 
 
-def flip_bound(theta, norm, g, fp8=False) -> np.ndarray:
+def flip_bound(theta, norm, g, fp8=False, infer=True) -> np.ndarray:
     """B2 per site: the largest |change of g_hat_p| / w_p over populations
     that one BF16 rounding flip of one second-layer activation can cause at
     each of the sites g (n, 37): h2_j rounded to the neighbouring BF16 value,
-    one unit in the last place at its own magnitude. Returns (n,).
+    one unit in the last place at its own magnitude. Returns (n,). infer:
+    h2 and W3 of the inference form (binary16, or the FP8 form's); else of
+    the BF16 training form. In the binary16 form a hidden activation's flip
+    is 2^-3 of this unit; the unit stays the BF16 one because the network's
+    inputs are BF16 in every form and their flips reach the output too.
 
     Why flips set the tolerance: the GPU kernels and the emulating forward
     pass round the same quantities to BF16 at the same points; the values
@@ -384,9 +441,9 @@ def flip_bound(theta, norm, g, fp8=False) -> np.ndarray:
     most 4 B2 of its site."""
     w = constants()["w"]
     p = unpack(theta)
-    W3 = np.abs(bf16(p["W3"]))
+    W3 = np.abs(f16(p["W3"]) if infer and not fp8 else bf16(p["W3"]))
     zs = (np.asarray(g, dtype=np.float64) / w - norm[0]) / norm[1]
-    _, (_, _, _, _, h2) = forward(theta, zs, emulate=True, fp8=fp8)
+    _, (_, _, _, _, h2) = forward(theta, zs, emulate=True, fp8=fp8, infer=infer)
     v = np.asarray(norm[3], dtype=np.float64)[:, None] * W3          # (37 outputs, 128 units)
     phi = np.abs(_basis())
     proj = phi.T @ ((phi * w) @ v / np.diag(gram())[:, None])

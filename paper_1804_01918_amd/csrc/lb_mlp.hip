@@ -112,7 +112,8 @@ __global__ __launch_bounds__(TB) void k_mlp_init(float* __restrict__ params, uin
     params[i] = (float)(a * (2.0 * u - 1.0));
 }
 
-// BF16 operand copies of the weights, zero padding included.
+// Operand copies of the weights, zero padding included: BF16 (training,
+// and the first layer of inference) and the binary16 W2p, W3p of inference.
 __global__ __launch_bounds__(TB) void k_mlp_pack(const float* __restrict__ params, uint16_t* __restrict__ W1b,
                                                  uint16_t* __restrict__ W2b, uint16_t* __restrict__ W3b,
                                                  uint16_t* __restrict__ W2t, uint16_t* __restrict__ W3t,
@@ -121,11 +122,11 @@ __global__ __launch_bounds__(TB) void k_mlp_pack(const float* __restrict__ param
     const int i = blockIdx.x * TB + threadIdx.x;
     if (i < HID * HID) {  // W2p[h2][slot]
         const int a = i / HID, slot = i % HID;
-        W2p[i] = bf16_bits(params[OFF_W2 + a * HID + chain_hidden(slot)]);
+        W2p[i] = f16_bits(params[OFF_W2 + a * HID + chain_hidden(slot)]);
     }
     if (i < NOUT * HID) {  // W3p[o][slot]
         const int o = i / HID, slot = i % HID;
-        W3p[i] = o < Q ? bf16_bits(params[OFF_W3 + o * HID + chain_hidden(slot)]) : 0;
+        W3p[i] = o < Q ? f16_bits(params[OFF_W3 + o * HID + chain_hidden(slot)]) : 0;
     }
     if (i < HID * KIN) {  // W1b[h][f], W3t[h][o]
         const int h = i / KIN, f = i % KIN;
@@ -524,13 +525,26 @@ __global__ __launch_bounds__(TB) void k_mlp_update(float* __restrict__ params, f
         const int j = i - OFF_W2, h2 = j / HID, h1 = j % HID;
         W2b[h2 * HID + h1] = b;
         W2t[h1 * HID + h2] = b;
-        W2p[h2 * HID + chain_slot(h1)] = b;
+        W2p[h2 * HID + chain_slot(h1)] = f16_bits(p);
     } else if (i >= OFF_W3 && i < OFF_B3) {
         const int j = i - OFF_W3, o = j / HID, h = j % HID;
         W3b[o * HID + h] = b;
         W3t[h * KIN + o] = b;
-        W3p[o * HID + chain_slot(h)] = b;
+        W3p[o * HID + chain_slot(h)] = f16_bits(p);
     }
+}
+
+// The binary16 GELU of the inference form on x[0..n): two values per lane,
+// through the same packed instructions as the hidden layers.
+__global__ __launch_bounds__(TB) void k_gelu16(const uint16_t* __restrict__ x, uint16_t* __restrict__ y, int64_t n)
+{
+    const int64_t i = 2 * ((int64_t)blockIdx.x * TB + threadIdx.x);
+    if (i >= n) return;
+    const float a = (float)__builtin_bit_cast(_Float16, x[i]);
+    const float b = i + 1 < n ? (float)__builtin_bit_cast(_Float16, x[i + 1]) : 0.0f;
+    const uint32_t r = gelu_h2(a, b);
+    y[i] = (uint16_t)r;
+    if (i + 1 < n) y[i + 1] = (uint16_t)(r >> 16);
 }
 
 // Learned equilibrium of n shifted-population sites (one per lane), with the
@@ -760,7 +774,7 @@ int lb_mlp_create(lb_mlp** out, void* workspace, size_t bytes, int32_t max_batch
     m->b1s = (float*)(ws + l.b1s);
     m->b2s = (float*)(ws + l.b2s);
     m->gk2 = (float*)(ws + l.gk2);
-    m->precision = LB_MLP_BF16;
+    m->precision = LB_MLP_F16;
     m->norm = (float*)(ws + l.norm);
     m->fnorm = (float*)(ws + l.fnorm);
     m->partials = (float*)(ws + l.partials);
@@ -981,13 +995,23 @@ int lb_mlp_equilibrium(lb_mlp* m, const float* pre, int64_t n, float threshold, 
 int lb_mlp_set_precision(lb_mlp* m, int32_t precision)
 {
     if (!m) return mfail(nullptr, LB_EINVAL, "lb_mlp_set_precision: NULL network");
-    if (precision != LB_MLP_BF16 && precision != LB_MLP_FP8)
+    if (precision != LB_MLP_F16 && precision != LB_MLP_FP8)
         return mfail(m, LB_EINVAL, "lb_mlp_set_precision: unknown precision %d", precision);
     m->precision = precision;
     return precision == LB_MLP_FP8 ? launch_pack_fp8(m) : LB_OK;
 }
 
 int lb_mlp_get_precision(const lb_mlp* m) { return m ? m->precision : LB_EINVAL; }
+
+int lb_mlp_gelu16(const uint16_t* x, uint16_t* y, int64_t n, void* stream)
+{
+    if (!x || !y || n < 0) return mfail(nullptr, LB_EINVAL, "lb_mlp_gelu16: bad argument");
+    if (n == 0) return LB_OK;
+    const int64_t pairs = (n + 1) / 2;
+    if (pairs > (int64_t)TB * 0x7fffffff) return mfail(nullptr, LB_EINVAL, "lb_mlp_gelu16: n is too large");
+    hipLaunchKernelGGL(k_gelu16, dim3((unsigned)((pairs + TB - 1) / TB)), dim3(TB), 0, (hipStream_t)stream, x, y, n);
+    return mcheck(nullptr, "lb_mlp_gelu16");
+}
 
 int lb_pairgen(float* pre, float* post, int64_t n, uint64_t seed, double tau, void* stream)
 {

@@ -32,7 +32,7 @@ struct lb_mlp {
     float* b1s;
     float* b2s;
     float* gk2;
-    int32_t precision;    // LB_MLP_BF16 or LB_MLP_FP8
+    int32_t precision;    // LB_MLP_F16 or LB_MLP_FP8
     float* norm;          // [4][64]
     float* fnorm;         // [4][64], folded from norm for inference (Net::fnorm)
     float* partials;      // [max_wg][NPARAM_PAD]

@@ -94,6 +94,49 @@ __device__ inline f32x4 mfma(bf16x8 a, bf16x8 b, f32x4 c)
     return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
 }
 
+// Binary16 (IEEE half) tiles: v_mfma_f32_16x16x32_f16 has the BF16 lane
+// layout; the hidden layers of inference run on it (see gelu_h2).
+typedef _Float16 f16x8 __attribute__((ext_vector_type(8)));
+typedef _Float16 f16x2 __attribute__((ext_vector_type(2)));
+typedef uint32_t u32x4v __attribute__((ext_vector_type(4)));
+__device__ inline f32x4 mfma_f16(u32x4v a, u32x4v b, f32x4 c)
+{
+    return __builtin_amdgcn_mfma_f32_16x16x32_f16(__builtin_bit_cast(f16x8, a), __builtin_bit_cast(f16x8, b), c, 0,
+                                                 0, 0);
+}
+__host__ __device__ inline uint16_t f16_bits(float f) { return __builtin_bit_cast(uint16_t, (_Float16)f); }
+
+// GELU of two FP32 pre-activations in binary16 arithmetic, packed in one
+// word (a low, b high): every operation rounds to nearest even in binary16,
+//   x = h(a), y = x (K1 x^2 + K2) (the K1 product and K2 sum fused), e = 2^y,
+//   r = 1 / (1 + e), result x r,
+// with K1, K2 of gelu_fast rounded to binary16. Packed instructions take
+// both halves at once; the hardware exponential and reciprocal of binary16
+// are correctly rounded (checked over every binary16 input), so the result
+// is a fixed function of (a, b) that a host can reproduce bit for bit. The
+// half-word results of the two transcendentals are written in place (SDWA):
+// the second write reads the first one's register, which needs one wait
+// state after a partial-register write on this GPU.
+__device__ inline uint32_t gelu_h2(float a, float b)
+{
+    const f16x2 x = __builtin_convertvector((float __attribute__((ext_vector_type(2)))){a, b}, f16x2);
+    const f16x2 k1 = {(_Float16)GELU_K1, (_Float16)GELU_K1}, k2 = {(_Float16)GELU_K2, (_Float16)GELU_K2};
+    const f16x2 y = x * __builtin_elementwise_fma(k1, x * x, k2);
+    uint32_t e, r;
+    asm("v_exp_f16_sdwa %0, %1 dst_sel:WORD_0 dst_unused:UNUSED_PRESERVE src0_sel:WORD_0\n\t"
+        "s_nop 0\n\t"
+        "v_exp_f16_sdwa %0, %1 dst_sel:WORD_1 dst_unused:UNUSED_PRESERVE src0_sel:WORD_1"
+        : "=&v"(e)
+        : "v"(__builtin_bit_cast(uint32_t, y)));
+    const f16x2 d = __builtin_bit_cast(f16x2, e) + (f16x2){(_Float16)1, (_Float16)1};
+    asm("v_rcp_f16_sdwa %0, %1 dst_sel:WORD_0 dst_unused:UNUSED_PRESERVE src0_sel:WORD_0\n\t"
+        "s_nop 0\n\t"
+        "v_rcp_f16_sdwa %0, %1 dst_sel:WORD_1 dst_unused:UNUSED_PRESERVE src0_sel:WORD_1"
+        : "=&v"(r)
+        : "v"(__builtin_bit_cast(uint32_t, d)));
+    return __builtin_bit_cast(uint32_t, x * __builtin_bit_cast(f16x2, r));
+}
+
 // FP8 (e4m3, the OCP variant without infinities) tiles:
 // v_mfma_f32_16x16x32_fp8_fp8 has the lane layout above with eight one-byte
 // values per lane (one 64-bit register pair per operand).
@@ -140,16 +183,18 @@ __host__ __device__ constexpr int chain_slot(int hidden)
     return (hidden & ~31) + 8 * ((hidden & 15) >> 2) + (hidden & 3) + ((hidden & 16) ? 4 : 0);
 }
 
-// Device view of a network: BF16 operand copies, FP32 biases (inside the
-// packed parameters) and the standardisation of inputs and outputs.
+// Device view of a network: BF16 operand copies (training, and the first
+// layer of inference), binary16 copies of W2 and W3 (inference), FP32 biases
+// (inside the packed parameters) and the standardisation of inputs and
+// outputs.
 struct Net {
     const uint16_t* W1b;  // [128][64]  W1[h][f], f padded with zeros
     const uint16_t* W2b;  // [128][128] W2[h2][h1]
     const uint16_t* W3b;  // [48][128]  W3[o][h], o padded with zeros
     const uint16_t* W2t;  // [128][128] W2[h2][h1] at [h1][h2]
     const uint16_t* W3t;  // [128][64]  W3[o][h] at [h][o], o padded
-    const uint16_t* W2p;  // [128][128] W2[h2][chain_hidden(slot)] at [h2][slot]
-    const uint16_t* W3p;  // [48][128]  W3[o][chain_hidden(slot)] at [o][slot], o padded
+    const uint16_t* W2p;  // [128][128] W2[h2][chain_hidden(slot)] at [h2][slot], binary16
+    const uint16_t* W3p;  // [48][128]  W3[o][chain_hidden(slot)] at [o][slot], o padded, binary16
     const float* params;  // packed FP32 parameters (biases read from here)
     const float* norm;    // [4][64]: mean z, 1/sd z, mean y, sd y
     const float* fnorm;   // [4][64] folded for inference: 1/(sd_z w), -mean_z/sd_z, w sd_y, w mean_y

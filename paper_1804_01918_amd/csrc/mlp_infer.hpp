@@ -2,8 +2,10 @@
 // on the matrix cores (see mlp_common.hpp for the fragment layout).
 //
 // For shifted populations g (37 per lane):
-//   z = g / w, standardised -> MLP 37-128-128-37 (GELU, BF16 operands,
-//   FP32 accumulation) -> y = mean_y + sd_y * o -> d = w y;
+//   z = g / w, standardised -> MLP 37-128-128-37 (first layer on BF16
+//   operands; the hidden activations, their GELU arithmetic and the weights
+//   of the last two layers in binary16; FP32 accumulation) ->
+//   y = mean_y + sd_y * o -> d = w y;
 //   g_hat = P(g) + d - P(d)   (P: the conserved part; mass, momentum and
 //   energy of g_hat are those of g);
 //   residual = largest deviation of g_hat's stress and heat flux from the
@@ -135,7 +137,7 @@ __device__ inline void network_outputs(const Net& net, uint16_t* X)
         k1 = net.gk2[0];
         k2 = net.gk2[1];
     }
-    typedef typename std::conditional<FP8, uint64_t, bf16x8>::type W2Frag;
+    typedef typename std::conditional<FP8, uint64_t, u32x4v>::type W2Frag;
     wave_sync();
 
 #pragma unroll 1
@@ -151,8 +153,9 @@ __device__ inline void network_outputs(const Net& net, uint16_t* X)
         // layer 1: tile mt of H1^T (16 units x 32 sites) = W1 X^T + b1 (row
         // 4 quad + j of the tile is unit 16 mt + 4 quad + j); its GELUs fill
         // slots 4 (mt & 1) + j of k block mt / 2 of the hidden layer's B
-        // fragments (FP8: e4m3 bytes, word mt & 1 of the 8-byte fragment)
-        bf16x8 hb[4][2];
+        // fragments: binary16 pairs, words 2 (mt & 1), 2 (mt & 1) + 1 (FP8:
+        // e4m3 bytes, word mt & 1 of the 8-byte fragment)
+        u32x4v hh[4][2];
         uint32_t hq[4][2][2];
         {
             bf16x8 w[2][2];  // [tile & 1][k step]
@@ -181,9 +184,9 @@ __device__ inline void network_outputs(const Net& net, uint16_t* X)
                         hq[mt >> 1][nt][mt & 1] = pack_fp8<true>(gelu16(a[b][nt][2]), gelu16(a[b][nt][3]), v);
                         asm volatile("" : "+v"(hq[mt >> 1][nt][mt & 1]));
                     } else {
-#pragma unroll
-                        for (int j = 0; j < 4; ++j) hb[mt >> 1][nt][4 * (mt & 1) + j] = to_bf16(gelu_fast(a[b][nt][j]));
-                        asm volatile("" : "+v"(hb[mt >> 1][nt]));
+                        hh[mt >> 1][nt][2 * (mt & 1)] = gelu_h2(a[b][nt][0], a[b][nt][1]);
+                        hh[mt >> 1][nt][2 * (mt & 1) + 1] = gelu_h2(a[b][nt][2], a[b][nt][3]);
+                        asm volatile("" : "+v"(hh[mt >> 1][nt]));
                     }
                 }
             };
@@ -198,10 +201,11 @@ __device__ inline void network_outputs(const Net& net, uint16_t* X)
             }
         }
 
-        // hidden layer: tile mt of H2^T = W2 H1^T + b2 (weight columns in
-        // chained order; FP8: H2^T 2^(aw + 4) = W2q H1q^T + b2s); last layer
-        // O^T (48 x 32) = W3 H2^T + b3 (outputs 37..47 zero), its k block kb
-        // taken once hidden tiles 2 kb and 2 kb + 1 are activated
+        // hidden layer: tile mt of H2^T = W2 H1^T + b2 (binary16 weights,
+        // columns in chained order; FP8: H2^T 2^(aw + 4) = W2q H1q^T + b2s);
+        // last layer O^T (48 x 32) = W3 H2^T + b3 (outputs 37..47 zero;
+        // binary16, FP8: BF16), its k block kb taken once hidden tiles 2 kb
+        // and 2 kb + 1 are activated
         f32x4 acc3[3][2];
 #pragma unroll
         for (int m3 = 0; m3 < 3; ++m3)
@@ -212,13 +216,13 @@ __device__ inline void network_outputs(const Net& net, uint16_t* X)
             }
         {
             W2Frag w[2][4];  // [tile & 1][k block]
-            bf16x8 w3[3], h2[2];
+            u32x4v w3[3], h2[2];  // binary16 pairs (FP8: BF16 pairs)
             f32x4 bias[2], a[2][2];
             auto load = [&](int mt) {
 #pragma unroll
                 for (int kb = 0; kb < 4; ++kb) {
                     if constexpr (FP8) w[mt & 1][kb] = frag8_im(net.W2q, net.ldq, mt * 16, kb * 32);
-                    else w[mt & 1][kb] = frag_im(net.W2p, net.ld23, mt * 16, kb * 32);
+                    else w[mt & 1][kb] = __builtin_bit_cast(u32x4v, frag_im(net.W2p, net.ld23, mt * 16, kb * 32));
                 }
                 bias[mt & 1] = bias4(b2 + 16 * mt + 4 * quad);
             };
@@ -233,20 +237,31 @@ __device__ inline void network_outputs(const Net& net, uint16_t* X)
                             a[b][nt] = mfma_fp8(w[b][kb], (uint64_t)hq[kb][nt][0] | ((uint64_t)hq[kb][nt][1] << 32),
                                                 a[b][nt]);
                         else
-                            a[b][nt] = mfma(w[b][kb], hb[kb][nt], a[b][nt]);
+                            a[b][nt] = mfma_f16(w[b][kb], hh[kb][nt], a[b][nt]);
                     }
             };
             auto act = [&](int mt) {
                 const int b = mt & 1;
 #pragma unroll
-                for (int nt = 0; nt < 2; ++nt)
+                for (int nt = 0; nt < 2; ++nt) {
 #pragma unroll
-                    for (int j = 0; j < 4; ++j) h2[nt][4 * (mt & 1) + j] = to_bf16(gelu_k(a[b][nt][j], k1, k2));
+                    for (int j = 0; j < 2; ++j) {
+                        const float lo = a[b][nt][2 * j], hi = a[b][nt][2 * j + 1];
+                        h2[nt][2 * (mt & 1) + j] = FP8 ? pack_bf16(gelu_k(lo, k1, k2), gelu_k(hi, k1, k2))
+                                                       : gelu_h2(lo, hi);
+                    }
+                }
                 if (mt & 1) {
 #pragma unroll
                     for (int m3 = 0; m3 < 3; ++m3)
 #pragma unroll
-                        for (int nt = 0; nt < 2; ++nt) acc3[m3][nt] = mfma(w3[m3], h2[nt], acc3[m3][nt]);
+                        for (int nt = 0; nt < 2; ++nt) {
+                            if constexpr (FP8)
+                                acc3[m3][nt] = mfma(__builtin_bit_cast(bf16x8, w3[m3]), __builtin_bit_cast(bf16x8, h2[nt]),
+                                                    acc3[m3][nt]);
+                            else
+                                acc3[m3][nt] = mfma_f16(w3[m3], h2[nt], acc3[m3][nt]);
+                        }
                 }
             };
             load(0);
@@ -256,7 +271,8 @@ __device__ inline void network_outputs(const Net& net, uint16_t* X)
                 if (s + 1 < 8) load(s + 1);
                 if (s > 0 && ((s - 1) & 1)) {
 #pragma unroll
-                    for (int m3 = 0; m3 < 3; ++m3) w3[m3] = frag_im(W3, net.ld23, m3 * 16, ((s - 1) >> 1) * 32);
+                    for (int m3 = 0; m3 < 3; ++m3)
+                        w3[m3] = __builtin_bit_cast(u32x4v, frag_im(W3, net.ld23, m3 * 16, ((s - 1) >> 1) * 32));
                 }
                 if (s < 8) mul(s);
                 if (s > 0) act(s - 1);

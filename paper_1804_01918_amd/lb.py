@@ -97,6 +97,7 @@ _SIGNATURES = {
     "lb_pairgen": (ctypes.c_int, [_VP, _VP, _I64, ctypes.c_uint64, _D, _VP]),
     "lb_mlp_set_precision": (ctypes.c_int, [_VP, _I32]),
     "lb_mlp_get_precision": (ctypes.c_int, [_VP]),
+    "lb_mlp_gelu16": (ctypes.c_int, [_VP, _VP, _I64, _VP]),
     "lb_set_surrogate": (ctypes.c_int, [_VP, _VP, _D]),
     "lb_surrogate_counts": (ctypes.c_int, [_VP, _VP]),
 }
@@ -212,6 +213,17 @@ def _torch():
     return torch
 
 
+def gelu16(x, stream=None):
+    """The binary16 GELU of the inference form on a device int16/uint16
+    tensor of binary16 bit patterns; returns the result patterns (int16)."""
+    torch = _torch()
+    s = stream if stream is not None else torch.cuda.current_stream()
+    x = x.contiguous()
+    y = torch.empty_like(x)
+    _check(lib().lb_mlp_gelu16(x.data_ptr(), y.data_ptr(), x.numel(), s.cuda_stream), None, "lb_mlp_gelu16")
+    return y
+
+
 def device_copy(dst, src, stream=None):
     """Streaming copy kernel of the library (bandwidth reference)."""
     torch = _torch()
@@ -274,10 +286,11 @@ class Mlp:
     def init(self, seed: int):
         _mcheck(lib().lb_mlp_init(self.handle, seed), self.handle, "lb_mlp_init")
 
-    MLP_PRECISIONS = {"bf16": 0, "fp8": 1}
+    MLP_PRECISIONS = {"f16": 0, "fp8": 1}
 
     def set_precision(self, precision: str):
-        """Inference precision: "bf16", or "fp8" (the hidden layer in e4m3)."""
+        """Inference precision: "f16" (hidden activations and the last two
+        layers in binary16, the default), or "fp8" (the hidden layer in e4m3)."""
         _mcheck(lib().lb_mlp_set_precision(self.handle, self.MLP_PRECISIONS[precision]), self.handle,
                 "lb_mlp_set_precision")
 

@@ -74,8 +74,8 @@ def test_precision_switch_and_rejection(oracle_net):
     with pytest.raises(lb.LBError) as e:
         lb._mcheck(lb.lib().lb_mlp_set_precision(m.handle, 7), m.handle, "set_precision")
     assert e.value.code == lb.LB_EINVAL
-    m.set_precision("bf16")
-    assert m.get_precision() == "bf16"
+    m.set_precision("f16")
+    assert m.get_precision() == "f16"
     m.close()
 
 

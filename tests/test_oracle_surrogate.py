@@ -186,7 +186,7 @@ def test_flip_bound_covers_single_flips_anywhere(consts, trained):
     if trained:
         theta, _ = S.train(pre, post, tau, theta, norm, batch=256, epochs=2, lr0=3e-3, seed=8)
     sites = pre[::97]
-    B2s = S.flip_bound(theta, norm, sites)
+    B2s = S.flip_bound(theta, norm, sites, infer=False)
     p = S.unpack(theta)
     W1, W2, W3 = (S.bf16(p[k]) for k in ("W1", "W2", "W3"))
 
@@ -309,7 +309,7 @@ def test_fp8_flip_bound_covers_planted_flips(consts):
     theta = S.init_params(6)
     sites = pre[::67]
     B1 = S.fp8_flip_bound(theta, norm, sites)
-    B2 = S.flip_bound(theta, norm, sites)
+    B2 = S.flip_bound(theta, norm, sites, fp8=True)
     p = S.unpack(theta)
     sw = 2.0 ** S.fp8_weight_exponent(p["W2"])
     W2q = S.e4m3(p["W2"] * sw) / sw
@@ -332,3 +332,118 @@ def test_fp8_flip_bound_covers_planted_flips(consts):
             moved = ghat(g[None, :], v)
             worst = max(worst, float(np.max(np.abs(moved - base) / w) / (B1[i] + 8 * B2[i])))
     assert worst <= 1.0, worst
+
+
+# ---- the inference form's binary16 hidden layer ---------------------------------------
+
+def test_f16_rounding_examples():
+    """Binary16 rounding: 11 significant bits, ties to even, subnormals down
+    to 2^-24 (ties to even there too), overflow at 65520 and beyond."""
+    cases = [(1.0 + 2.0 ** -11, 1.0), (1.0 + 3 * 2.0 ** -11, 1.0 + 2.0 ** -9), (1.0 + 2.0 ** -11 + 2.0 ** -30, 1.0 + 2.0 ** -10),
+             (65504.0, 65504.0), (65519.99, 65504.0), (2.0 ** -25, 0.0), (1.5 * 2.0 ** -24, 2.0 ** -23),
+             (-2.302734375, -2.302734375), (0.1, 0.0999755859375)]
+    for v, want in cases:
+        assert S.f16(v) == want, (v, S.f16(v), want)
+    assert np.isinf(S.f16(65520.0)) and np.isinf(S.f16(-1e6))
+
+
+def test_gelu_f16_constants_and_special_values():
+    """K1 = -2 log2(e) c A and K2 = -2 log2(e) c (c = sqrt(2/pi), A = 0.044715)
+    on the binary16 grid; gelu(0) = 0, large positive inputs come back
+    unchanged, large negative ones give -0, and 1 and -1 are worked by hand."""
+    l2e = 1.0 / math.log(2.0)
+    assert S.GELU_K1_F16 == -0.10296630859375 == S.f16(-2 * l2e * math.sqrt(2 / math.pi) * 0.044715)
+    assert S.GELU_K2_F16 == -2.302734375 == S.f16(-2 * l2e * math.sqrt(2 / math.pi))
+    v = S.gelu_f16(np.array([0.0, 300.0, 60000.0, -300.0, 20.0]))
+    assert v[0] == 0.0 and v[1] == 300.0 and v[2] == 60000.0 and v[3] == 0.0 and np.signbit(v[3]) and v[4] == 20.0
+    # a = 1: s = 1, t = h(K1 + K2) = -2.40625, y = -2.40625, e = h(2^-2.40625)
+    e = S.f16(2.0 ** -2.40625)
+    assert S.f16(S.GELU_K1_F16 + S.GELU_K2_F16) == -2.40625
+    r = S.f16(1.0 / S.f16(e + 1.0))
+    assert S.gelu_f16(np.array([1.0]))[0] == r
+    assert abs(r - S.gelu(1.0)) < 2 ** -10
+    # a = -1: y = h(-1 * h(K1 + K2)) = 2.40625, result -h(1 / h(2^2.40625 + 1))
+    assert S.gelu_f16(np.array([-1.0]))[0] == -S.f16(1.0 / S.f16(S.f16(2.0 ** 2.40625) + 1.0))
+
+
+def test_gelu_f16_follows_gelu_on_every_binary16_input():
+    """Over every binary16 value in [-12, 12] the binary16 evaluation stays
+    within 1 % + 2^-13 of the tanh form in FP64 (seven roundings, and the
+    exponential's amplification of the rounded exponent); a halved K1 or
+    K2, a dropped cubic or the natural exponential instead of 2^y each
+    break that by more than 0.01."""
+    x = np.arange(65536, dtype=np.uint16).view(np.float16).astype(np.float64)
+    x = x[np.isfinite(x) & (np.abs(x) <= 12)]
+    exact = S.gelu(x)
+    assert np.max(np.abs(S.gelu_f16(x) - exact) - 0.01 * np.abs(exact)) <= 2.0 ** -13
+    # the mutants, evaluated with the same roundings
+    xx = S.f16(x)
+    for k1f, k2f, base in ((0.5, 1.0, 2.0), (1.0, 0.5, 2.0), (0.0, 1.0, 2.0), (1.0, 1.0, math.e)):
+        t = S.f16(S.GELU_K1_F16 * k1f * S.f16(xx * xx) + S.GELU_K2_F16 * k2f)
+        m = S.f16(xx * S.f16(1.0 / S.f16(S.f16(base ** S.f16(xx * t)) + 1.0)))
+        assert np.max(np.abs(m - exact) - 0.01 * np.abs(exact)) > 0.01
+
+
+def test_f16_forward_rounds_only_the_hidden_layer():
+    """The inference form keeps the first layer and its BF16 inputs, puts
+    both hidden layers' activations on the binary16 grid, and differs from
+    the BF16 training form by about the BF16 rounding it no longer does."""
+    tau = 0.8
+    pre, post = S.make_pairs(512, seed=3, tau=tau)
+    norm = S.fit_normalization(pre, post, tau)
+    theta = S.init_params(2)
+    zs = (pre / S.constants()["w"] - norm[0]) / norm[1]
+    oh, (xh, a1h, h1h, _, h2h) = S.forward(theta, zs, emulate=True, infer=True)
+    ob, (xb, a1b, _, _, _) = S.forward(theta, zs, emulate=True)
+    assert np.array_equal(xh, xb) and np.array_equal(a1h, a1b)
+    assert np.array_equal(S.f16(h1h), h1h) and np.array_equal(S.f16(h2h), h2h)
+    rel = np.abs(oh - ob).max() / np.abs(ob).max()
+    assert 1e-5 < rel < 0.05, rel
+    # and the FP8 form is untouched by infer
+    o8a, _ = S.forward(theta, zs, emulate=True, fp8=True)
+    o8b, _ = S.forward(theta, zs, emulate=True, fp8=True, infer=True)
+    assert np.array_equal(o8a, o8b)
+
+
+def test_flip_bound_covers_planted_flips_in_the_f16_form(consts):
+    """In the binary16 inference form: one BF16 flip of one input, or one
+    binary16 flip (one unit in the last place, either direction) of one
+    first- or second-layer activation, everything downstream rounded again
+    as the form does: g_hat moves by at most 4 B2 of the site."""
+    w = consts["w"]
+    tau = 0.8
+    pre, post = S.make_pairs(2048, seed=21, tau=tau)
+    norm = S.fit_normalization(pre, post, tau)
+    theta, _ = S.train(pre, post, tau, S.init_params(4), norm, batch=256, epochs=2, lr0=3e-3, seed=8)
+    sites = pre[::131]
+    B2s = S.flip_bound(theta, norm, sites)
+    p = S.unpack(theta)
+    W1, W2, W3 = S.bf16(p["W1"]), S.f16(p["W2"]), S.f16(p["W3"])
+
+    def f16_ulp(v):
+        a = abs(v)
+        return 2.0 ** (max(math.floor(math.log2(a)), -14) - 10) if a > 0 else 2.0 ** -24
+
+    def ghat(g, x=None, h1=None, h2=None):
+        if h1 is None:
+            h1 = S.gelu_f16(S.f32(x @ W1.T + p["b1"]))
+        if h2 is None:
+            h2 = S.gelu_f16(S.f32(h1 @ W2.T + p["b2"]))
+        d = w * (norm[2] + norm[3] * (h2 @ W3.T + p["b3"]))
+        return S.conserved_part(g) + d - S.conserved_part(d), h1, h2
+
+    rng = np.random.default_rng(5)
+    worst = 0.0
+    for g, B2 in zip(sites, B2s):
+        g = g[None, :]
+        x = S.bf16((g / w - norm[0]) / norm[1])
+        base, h1, h2 = ghat(g, x=x)
+        for kind, n in (("x", 37), ("h1", 128), ("h2", 128)):
+            for k in range(n):
+                v = {"x": x, "h1": h1, "h2": h2}[kind].copy()
+                step = S.bf16_ulp(v[0, k]) if kind == "x" else f16_ulp(v[0, k])
+                v[0, k] += rng.choice([-1.0, 1.0]) * step
+                args = {"x": dict(x=v), "h1": dict(h1=v), "h2": dict(h1=h1, h2=v)}[kind]
+                moved, _, _ = ghat(g, **args)
+                worst = max(worst, float(np.max(np.abs(moved - base) / w) / B2))
+    assert worst <= 4.0, worst
