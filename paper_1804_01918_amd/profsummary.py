@@ -95,9 +95,11 @@ def main():
     ap.add_argument("--sources", choices=("plain", "learned"), default="plain",
                     help="which kernel sources the digest of the entry covers")
     ap.add_argument("--alg-flops", type=float, default=0.0, help="algorithmic matrix-core flops per launch")
-    ap.add_argument("--valu", default=None,
-                    help="a --pmc run of the SQ_INSTS_VALU_{FMA,MUL,ADD,TRANS}_F64/_F32 counters: vector flops")
-    ap.add_argument("--valu-counters", default="", help="the counter names that run collected (space separated)")
+    ap.add_argument("--valu", action="append", default=[],
+                    help="a --pmc run of SQ_* counters (repeatable, paired with --valu-counters); the "
+                         "SQ_INSTS_VALU_{FMA,MUL,ADD,TRANS}_F64/_F32 ones give vector flops")
+    ap.add_argument("--valu-counters", action="append", default=[],
+                    help="the counter names that run collected (space separated)")
     a = ap.parse_args()
     files = PLAIN_SOURCES if a.sources == "plain" else LEARNED_SOURCES
     digest = source_digest(files)
@@ -117,13 +119,18 @@ def main():
                   f"{a.alg_flops / (avg_us * 1e-6) / 1e12:.1f} TFLOP/s.", ""]
 
     if a.valu and a.valu_counters:
-        # Each counter counts wavefront instructions; x64 lanes, FMA = 2 flops.
+        # Each counter counts wavefront instructions; x64 lanes, FMA = 2 flops
+        # (FP32 and FP64 counters; binary16 ones are listed only: a packed
+        # instruction does two operations per lane).
         vals = {}
-        for cname in a.valu_counters.split():
-            _, cv = _pick(counter_per_dispatch(a.valu, cname), a.match)
-            vals[cname] = statistics.median(cv)
+        for run, names in zip(a.valu, a.valu_counters):
+            for cname in names.split():
+                _, cv = _pick(counter_per_dispatch(run, cname), a.match)
+                vals.setdefault(cname, statistics.median(cv))
         flops = 0.0
         for cname, v in vals.items():
+            if not (cname.endswith("_F32") or cname.endswith("_F64")):
+                continue
             if "_FMA_" in cname:
                 flops += 2 * 64 * v
             elif any(k in cname for k in ("_MUL_", "_ADD_", "_TRANS_")):
@@ -131,7 +138,13 @@ def main():
         lines += ["## Vector ALU work (--pmc, medians per dispatch)", "", "| counter | per dispatch | per site |",
                   "|---|---|---|"]
         for cname, v in vals.items():
-            lines.append(f"| {cname} | {v:.4g} | {64 * v / a.sites:.1f} lane-ops |")
+            if cname.startswith("SQ_ACTIVE") or cname in ("SQ_WAVE_CYCLES", "SQ_WAIT_ANY", "SQ_WAIT_INST_ANY"):
+                unit = "quad-cycles per 64 sites"   # counted in units of 4 cycles
+            elif "CYCLES" in cname:
+                unit = "cycles per 64 sites"
+            else:
+                unit = "lane-ops"
+            lines.append(f"| {cname} | {v:.4g} | {64 * v / a.sites:.1f} {unit} |")
         lines += ["", f"Counted vector flops (FMA = 2): {flops / a.sites:.0f} per site, "
                       f"{flops / (avg_us * 1e-6) / 1e12:.2f} TFLOP/s at the traced launch time.", ""]
         valu_flops_per_site = flops / a.sites
