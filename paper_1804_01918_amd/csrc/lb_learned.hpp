@@ -3,7 +3,7 @@
 // per site to the plain FP32 collide; fallback and site counts are
 // accumulated in two 64-bit counters.
 //
-// Persistent launch: one 512-lane workgroup per compute unit copies the BF16
+// Persistent launch: one 512-lane workgroup per compute unit copies the
 // weights into LDS once and then walks 512-site row tiles (a tile is a run
 // of one lattice row; the tiles of an XCD are contiguous). Each wavefront
 // stages its 64 sites' inputs in its own LDS rows, runs the network, then

@@ -313,7 +313,8 @@ struct SharedWeights {
 };
 static_assert(HID * LDWQ <= HID * LDW23 * 2, "the e4m3 W2 copy fits the W2 area");
 
-// Copy the inference weights of `net` (BF16, or the FP8 form's) into LDS
+// Copy the inference weights of `net` (BF16 W1 and binary16 W2, W3, or the FP8
+// form's) and its biases into LDS
 // (all threads of the workgroup; the caller synchronises) and return the
 // view that reads them.
 template <int NTHREADS, bool FP8>
