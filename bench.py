@@ -277,6 +277,41 @@ def table1_variant(args, torch, lb, inputs):
                                 for k, (a, b) in TABLE1.items()}}
 
 
+def graph_variant(args, torch, lb, inputs):
+    """The small 128 x 64 lattice (8,192 sites: a few microseconds of GPU
+    work per step, so launches dominate): FP64 CAoSoA steps launched one by
+    one from the library's loop against the same steps captured once into a
+    HIP graph (torch.cuda.CUDAGraph over lb_step) and replayed."""
+    lx, ly, per, reps = 128, 64, 100, 20
+    fields = [torch.from_numpy(a).cuda() for a in inputs.shear_wave(lx, ly, seed=0)]
+    cap = torch.cuda.Stream()
+    with torch.cuda.stream(cap):
+        lat = lb.Lattice(lx, ly, TAU, fields, precision="f64", layout="caosoa")
+        lat.step(10)
+    torch.cuda.synchronize()
+    t_eager = time_calls(lat, torch, lambda: lat.step(per), reps)
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph, stream=cap):
+        lat.step(per)
+    torch.cuda.synchronize()
+    graph.replay()
+    torch.cuda.synchronize()
+    start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    start.record(cap)
+    for _ in range(reps):
+        graph.replay()
+    stop.record(cap)
+    stop.synchronize()
+    t_graph = start.elapsed_time(stop) / 1e3
+    lat.close()
+    del lat, graph
+    torch.cuda.empty_cache()
+    n = lx * ly * per * reps
+    return {"lattice": [lx, ly], "precision": "f64", "layout": "caosoa", "steps": per * reps,
+            "us_per_step_launched": t_eager / (per * reps) * 1e6, "us_per_step_graph": t_graph / (per * reps) * 1e6,
+            "mlups_launched": n / t_eager / 1e6, "mlups_graph": n / t_graph / 1e6}
+
+
 def energy_variant(args, torch, lb, fields, net):
     """Package power on the GPU's energy counter while a kernel loop runs
     (2048 x 2048 shear wave, about 3 s per loop), times the loop's GPU time:
@@ -577,6 +612,7 @@ def main():
         out["roofline"]["frac_of_copy"] = achieved / cb
 
         variants["table1_1024x8192_f64"] = table1_variant(args, torch, lb, inputs)
+        variants["graph_replay_128x64_f64"] = graph_variant(args, torch, lb, inputs)
 
         # Precision on the thermal Rayleigh-Taylor-like state.
         rt = (LX, LY, [torch.from_numpy(a).cuda() for a in inputs.rayleigh_taylor(LX, LY, seed=0)])
