@@ -184,3 +184,13 @@ def test_strerror():
 def test_copy_rejects_misaligned():
     assert lb.lib().lb_copy(0x1000, 0x2008, 64, None) == lb.LB_EINVAL
     assert lb.lib().lb_copy(0x1000, 0x2000, 63, None) == lb.LB_EINVAL
+
+
+def test_gelu16_rejects_bad_arguments():
+    """Validated on the host before any launch: NULL pointers and negative
+    counts are LB_EINVAL; n = 0 is a no-op."""
+    L = lb.lib()
+    assert L.lb_mlp_gelu16(None, 0x2000, 4, None) == lb.LB_EINVAL
+    assert L.lb_mlp_gelu16(0x1000, None, 4, None) == lb.LB_EINVAL
+    assert L.lb_mlp_gelu16(0x1000, 0x2000, -1, None) == lb.LB_EINVAL
+    assert L.lb_mlp_gelu16(0x1000, 0x2000, 0, None) == lb.LB_OK
