@@ -39,6 +39,7 @@ struct lb_ctx {
     double* wall_tab;      // scratch: [2][WALL_TAB] (walls only)
     int device;            // device current at lb_init (where the buffers live)
     void* static_scratch;  // that device's address of `scratch` (lb_audit_static), or NULL
+    bool f16_stream_stores;  // FP16 buffers of at least STREAM_STORE_BYTES: hinted stores in lb_step
     char err[512];
 };
 
@@ -50,6 +51,11 @@ struct lb_ctx {
 // ends. Host code never passes the array's name to a kernel or a copy: it
 // uses the device address that hipGetSymbolAddress returns for the current
 // device, resolved once per device by lb_init.
+// FP16 buffers from this size on (each) are stepped with hinted stores
+// (PrecF16SN): at 2048^2 (310 MB) the cached stores are faster, at 4096^2
+// (1.24 GB) the hinted ones; the GPU's last-level cache holds 256 MB.
+constexpr size_t STREAM_STORE_BYTES = (size_t)512 << 20;
+
 constexpr int64_t STATIC_AUDIT_MAX_TILES = (int64_t)1 << 18;  // 8192 x 8192 sites
 constexpr size_t STATIC_SCRATCH_BYTES = (size_t)(STATIC_AUDIT_MAX_TILES * 4 + 4) * sizeof(double);
 static __device__ __align__(256) double scratch[STATIC_AUDIT_MAX_TILES * 4 + 4];
@@ -311,6 +317,7 @@ int lb_init(lb_ctx** out, const lb_config* cfg, const double* rho, const double*
     c->err[0] = 0;
     c->device = -1;
     c->static_scratch = nullptr;
+    c->f16_stream_stores = k.precision == LB_FP16_SHIFTED && bb >= STREAM_STORE_BYTES;
     if (hipGetDevice(&c->device) == hipSuccess) {
         hipError_t e;
         c->static_scratch = static_scratch_of(c->device, &e);
@@ -444,18 +451,27 @@ int lb_step(lb_ctx* c, int32_t nsteps)
             const auto* src = (const typename P::T*)cur_buf(c);
             auto* dst = (typename P::T*)other_buf(c);
             const auto force = force_of<typename P::C>(c);
-#define D2Q37_STEP(CMP, AUD, FRC)                                                                              \
-    hipLaunchKernelGGL((k_step<P, L, CMP, AUD, FRC>), grid_of(c), dim3(BLOCK), 0, c->stream, src, dst, c->geo, omega, \
+            auto launch = [&](auto pk) {
+                using PK = decltype(pk);  // P, or its hinted-store form
+#define D2Q37_STEP(CMP, AUD, FRC)                                                                                 \
+    hipLaunchKernelGGL((k_step<PK, L, CMP, AUD, FRC>), grid_of(c), dim3(BLOCK), 0, c->stream, src, dst, c->geo, omega, \
                        c->partials, force)
 #define D2Q37_STEP_BC(CMP, AUD) \
     do { if (c->forced) D2Q37_STEP(CMP, AUD, true); else D2Q37_STEP(CMP, AUD, false); } while (0)
-            if (comp) {
-                if (audit) D2Q37_STEP_BC(true, true); else D2Q37_STEP_BC(true, false);
-            } else {
-                if (audit) D2Q37_STEP_BC(false, true); else D2Q37_STEP_BC(false, false);
-            }
+                if (comp) {
+                    if (audit) D2Q37_STEP_BC(true, true); else D2Q37_STEP_BC(true, false);
+                } else {
+                    if (audit) D2Q37_STEP_BC(false, true); else D2Q37_STEP_BC(false, false);
+                }
 #undef D2Q37_STEP_BC
 #undef D2Q37_STEP
+            };
+            if constexpr (P::kind == PREC_F16S) {
+                if (c->f16_stream_stores) launch(PrecF16SN{});
+                else launch(P{});
+            } else {
+                launch(P{});
+            }
         });
         const int rc = launch_status(c, "lb_step");
         if (rc != LB_OK) return rc;

@@ -121,6 +121,19 @@ struct PrecF16S {
     }
 };
 
+// The same storage with the streaming hint on the fused step's stores, for
+// lattices whose buffers are far larger than the GPU's last-level cache:
+// there a cached store buys no reuse before the line is evicted, and the
+// hinted stores ran 4 % faster at 4096^2 and 8192^2 (at 2048^2, 310 MB per
+// buffer, the cached ones are 8 % faster).
+struct PrecF16SN : PrecF16S {
+    template <bool NT = true>
+    __device__ static void store(T* a, int p, C v)
+    {
+        st_stream<T, NT>(a, (uint16_t)__half_as_ushort(__float2half_rn(v * scale(p))));
+    }
+};
+
 template <class P>
 constexpr int vl_of() { return 128 / (int)sizeof(typename P::T); }
 

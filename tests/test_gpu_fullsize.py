@@ -123,3 +123,25 @@ def test_2048_conservation_1000_steps(consts, prec):
         A = float(np.max(np.abs(f0 - consts["w"][:, None, None]) / consts["w"][:, None, None]))
         xi2 = float(np.max((consts["xi"] ** 2).sum(1)))
         assert np.all(np.abs(a1 - a0) <= n * EPS[prec] * A * M * xi2), (a1 - a0)
+
+
+def test_4096_f16_fused_with_hinted_stores_equals_split():
+    """FP16 buffers of 512 MiB and more are stepped with hinted stores (a
+    separate instantiation of the fused kernel); the values must not
+    change: 4096^2 (1.24 GB per buffer), two fused steps against two
+    propagate + collide pairs (cached stores), bit for bit, and the same
+    for 2048^2 (310 MB, cached stores in both) as the control."""
+    for n in (2048, 4096):
+        fields = [torch.from_numpy(a).cuda() for a in inputs.rayleigh_taylor(n, n, seed=11)]
+        a = lb.Lattice(n, n, 0.8, fields, precision="f16s", layout="caosoa")
+        b = lb.Lattice(n, n, 0.8, fields, precision="f16s", layout="caosoa")
+        a.step(2)
+        for _ in range(2):
+            b.propagate()
+            b.collide()
+        torch.cuda.synchronize()
+        assert torch.equal(a.raw_state(), b.raw_state()), n
+        a.close()
+        b.close()
+        del fields
+        torch.cuda.empty_cache()
