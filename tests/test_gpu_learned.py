@@ -611,3 +611,44 @@ def test_gelu16_matches_oracle_on_every_binary16_input():
     assert bad.size == 0, [(float(x[~nan][i]), hex(gb[i]), hex(wb[i])) for i in bad[:8]]
     odd = lb.gelu16(torch.from_numpy(bits[:7].view(np.int16).copy()).cuda()).cpu().numpy().view(np.uint16)
     assert np.array_equal(odd, got[:7])
+
+
+def test_binary16_overflow_falls_back_without_leaking(consts, oracle_net):
+    """Sites whose moments lie inside the training box but whose populations
+    are far from equilibrium (a moment-free perturbation of 3e4 w_p) drive
+    the binary16 hidden layer past its largest value: the activations become
+    infinite, the outputs NaN, the residual NaN, and the verdict fallback, on
+    the device as in the oracle's emulation. Such a site must come back as
+    the plain equilibrium (finite), and the ordinary sites of the same call
+    must not notice (bars as in test_learned_equilibrium_matches_oracle)."""
+    theta, norm, _ = oracle_net
+    m = _gpu_net(theta, norm)
+    nf = m.get_normalization().astype(np.float64)
+    w = consts["w"]
+    pre, _ = S.make_pairs(1024, seed=41, tau=TAU)
+    rng = np.random.default_rng(5)
+    noise = rng.standard_normal(pre.shape) * w
+    noise = noise - S.conserved_part(noise)           # moment-free
+    wild = np.zeros(pre.shape[0], dtype=bool)
+    wild[::3] = True
+    pre = np.where(wild[:, None], pre + 3e4 * noise, pre)
+    pre = _f32(pre)
+    rho, ux, uy, T = S.macro(pre)
+    box = S.in_box(rho, ux, uy, T)
+    with np.errstate(all="ignore"):
+        z = (pre / w - nf[0]) / nf[1]
+        o, _ = S.forward(theta, z, emulate=True, infer=True)
+    assert np.all(np.isnan(o[wild & box]).any(axis=1))   # the emulation overflows too
+    gh, res, fb = m.equilibrium(_dev(pre), 1e9)
+    gh, fb = gh.cpu().numpy(), fb.cpu().numpy().astype(bool)
+    assert np.all(np.isfinite(gh))
+    assert np.all(fb[wild]) and np.array_equal(fb[~wild], ~box[~wild])
+    exact = lbm.init(rho[:, None], ux[:, None], uy[:, None], T[:, None])[:, :, 0].T - w
+    scale = np.max(np.abs(pre[wild]) / w, axis=1) + 1.0
+    assert np.max(np.max(np.abs(gh[wild] - exact[wild]) / w, axis=1) / scale) < 1e-5
+    keep = ~wild & box
+    with np.errstate(all="ignore"):
+        want = S.surrogate_equilibrium(pre[keep], theta, nf, emulate=True)
+    _check_sites(np.max(np.abs(gh[keep] - want) / w, axis=1), _bar(theta, nf, pre[keep]),
+                 what="ordinary sites beside overflowing ones")
+    m.close()
