@@ -1,5 +1,7 @@
 // Learned collide: shared device pieces of the MLP 37 -> 128 -> 128 -> 37
-// (GELU), run in BF16 on the gfx950 matrix cores with FP32 accumulation.
+// (GELU), run on the gfx950 matrix cores with FP32 accumulation: trained in
+// BF16, evaluated with a BF16 first layer and binary16 hidden layers (or an
+// FP8 hidden layer).
 //
 // Matrix-core tiles: v_mfma_f32_16x16x32_bf16 computes D(16x16) += A(16x32)
 // B(32x16). Lane l of the wavefront holds
