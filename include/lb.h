@@ -163,7 +163,11 @@ int lb_collide(lb_ctx *ctx);
  * current buffer, collides in registers and writes the other buffer, which
  * then becomes current (ping-pong). Bit-identical to nsteps x
  * (lb_propagate; lb_collide). nsteps = 0 is a no-op; LB_EINVAL for a NULL
- * context or nsteps < 0; LB_EDEVICE if a launch fails. Asynchronous. */
+ * context or nsteps < 0; LB_EDEVICE if a launch fails. Asynchronous. It
+ * allocates nothing, synchronises nothing and issues no memset, so the
+ * launches may be captured into a HIP graph on the context's stream and
+ * replayed; with an even nsteps the captured buffers alternate the same way
+ * on every replay. */
 int lb_step(lb_ctx *ctx, int32_t nsteps);
 
 /* Macroscopic fields of the current state (paper, Section 3: density,
