@@ -322,7 +322,9 @@ def energy_variant(args, torch, lb, fields, net):
     meter = EnergyMeter(0)
     out = {"available": meter.available, "reason": meter.reason or None,
            "method": "package power between energy-counter refreshes (about 1 s apart) inside the loop, "
-                     "times GPU time per call",
+                     "times GPU time per call; graphics clock and the share of the loop under "
+                     "package-power throttling from the metrics table at the same refreshes",
+           "power_cap_watts": meter.power_limit_watts(),
            "fused_step": {}, "f64_split_kernels_by_layout": {}}
     if not meter.available:
         return out
@@ -351,7 +353,8 @@ def energy_variant(args, torch, lb, fields, net):
         stop.synchronize()
         per_call = start.elapsed_time(stop) / 1e3 / n
         return {"calls": n, "gpu_s_per_call": per_call, "avg_watts": watts, "sampled_s": span,
-                "counter_refreshes": refreshes, "J_per_call": watts * per_call if watts is not None else None}
+                "counter_refreshes": refreshes, "J_per_call": watts * per_call if watts is not None else None,
+                "gfxclk_mhz": meter.last_clock_mhz, "power_throttled_share": meter.last_power_throttled}
 
     forms = [("f64", None), ("f32s", None), ("f16s", None)] + ([("f32s", net)] if net is not None else [])
     for prec, nn in forms:

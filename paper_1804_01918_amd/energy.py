@@ -12,6 +12,12 @@ and just after a short region can both return stale samples. The meter
 therefore enqueues the work, polls the counter while the GPU is busy, and
 takes the power between the first and the last refresh it sees inside the
 run, on the counter's own timestamps.
+
+At each refresh it also reads the device's metrics table: the current
+graphics clock and the firmware's residency counter for package-power
+throttling. Kernels that draw the board's power cap run below the
+nominal 2.4 GHz; `last_clock_mhz` and `last_power_throttled` say by how
+much and for what share of the run.
 """
 from __future__ import annotations
 
@@ -26,6 +32,8 @@ class EnergyMeter:
     def __init__(self, device: int = 0):
         self.available = False
         self.reason = ""
+        self.last_clock_mhz = None        # mean graphics clock over the last power_during run
+        self.last_power_throttled = None  # share of that run under package-power throttling
         self._smi = None
         self._h = None
         try:
@@ -53,6 +61,18 @@ class EnergyMeter:
         r = self._smi.amdsmi_get_energy_count(self._h)
         return r["energy_accumulator"] * r["counter_resolution"] * 1e-6, r["timestamp"]
 
+    def _metrics(self):
+        """(graphics clock in MHz or None, package-power throttle residency,
+        residency sample count) from the metrics table; the two counters
+        accumulate in the same firmware samples, so the ratio of their
+        differences is the throttled share of the time between two reads."""
+        try:
+            m = self._smi.amdsmi_get_gpu_metrics_info(self._h)
+        except Exception:
+            return None, None, None
+        num = lambda v: v if isinstance(v, int) else None  # noqa: E731  ("N/A" where unsupported)
+        return num(m.get("current_gfxclk")), num(m.get("ppt_residency_acc")), num(m.get("accumulation_counter"))
+
     def power_during(self, launch_chunk, nchunks: int, done, poll_s: float = 0.001):
         """Enqueue GPU work as nchunks calls of launch_chunk() (asynchronous;
         the counter is polled between chunks, since enqueueing blocks once
@@ -68,6 +88,7 @@ class EnergyMeter:
             return None, 0.0, 0
         _, ts = self._read()
         samples = []
+        metrics = []
 
         def poll():
             nonlocal ts
@@ -75,6 +96,7 @@ class EnergyMeter:
             if t != ts:
                 ts = t
                 samples.append((e, t))
+                metrics.append(self._metrics())
 
         for _ in range(nchunks):
             launch_chunk()
@@ -82,6 +104,13 @@ class EnergyMeter:
         while not done():
             poll()
             time.sleep(poll_s)
+        clocks = [c for c, _, _ in metrics if c]
+        self.last_clock_mhz = sum(clocks) / len(clocks) if clocks else None
+        self.last_power_throttled = None
+        if len(metrics) >= 2 and None not in metrics[0][1:] + metrics[-1][1:]:
+            dn = metrics[-1][2] - metrics[0][2]
+            if dn > 0:
+                self.last_power_throttled = (metrics[-1][1] - metrics[0][1]) / dn
         if len(samples) < 2:
             return None, 0.0, len(samples)
         (e0, t0), (e1, t1) = samples[0], samples[-1]

@@ -2,7 +2,8 @@
 to solution, Section 5 and Fig. 4): the package energy counter is there,
 the package power while the fused step runs lies between the idle power
 and the board's power cap, and the energy of a loop scales with its length
-(2N calls take twice the energy of N calls, within 10 %)."""
+(2N calls take twice the energy of N calls, within 10 %). The graphics
+clock and power-throttle share read beside it are in range."""
 import pytest
 
 pytestmark = pytest.mark.gpu
@@ -52,13 +53,21 @@ def test_energy_meter_on_the_fused_step():
         per_step = t0.elapsed_time(t1) / 1e3 / 200
         n = int(2.5 / per_step) // 10 * 10
         w1, s1, j1 = _loop_energy(meter, lat, n)
+        clk, thr = meter.last_clock_mhz, meter.last_power_throttled
         w2, s2, j2 = _loop_energy(meter, lat, 2 * n)
     cap = meter.power_limit_watts()
     meter.close()
     print(f"idle {idle} W ({nidle} refreshes); loop {w1:.0f} W for {s1:.2f} s, {w2:.0f} W for {s2:.2f} s; "
-          f"cap {cap} W; J(2N)/2J(N) = {j2 / (2 * j1):.3f}; {j1 / (n * L * L) * 1e9:.1f} nJ per lattice update")
+          f"cap {cap} W; J(2N)/2J(N) = {j2 / (2 * j1):.3f}; {j1 / (n * L * L) * 1e9:.1f} nJ per lattice update; "
+          f"graphics clock {clk} MHz, power-throttled share {thr}")
     assert idle is not None and idle > 0
     assert idle < w1 and idle < w2
     if cap is not None:
         assert w1 <= 1.05 * cap and w2 <= 1.05 * cap
     assert abs(j2 / (2 * j1) - 1) <= 0.10
+    # the metrics table, where the device has one: a clock within the part's
+    # range (nominal 2.4 GHz) and a throttled share between 0 and 1
+    if clk is not None:
+        assert 100 <= clk <= 2600
+    if thr is not None:
+        assert 0.0 <= thr <= 1.0 + 1e-9
