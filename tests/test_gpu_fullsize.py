@@ -4,6 +4,8 @@ benchmark times (2048 x 2048 and 8192 x 8192, CAoSoA layout, fused step).
 * Sampled parity: after n steps from the seeded state, sampled sites
   (random ones plus the corners and edges, where the periodic wrap acts) are
   compared with the oracle evaluated on each site's dependency window.
+* The longest rows the host accepts (in-row offsets at the 4 GiB limit of
+  the kernels' 32-bit lane offsets), sampled the same way.
 * Properties after 1000 steps: the shear wave decays at the rate kinetic
   theory gives, exp(-nu k^2 t) with nu = theta T (tau - 1/2), and the FP64
   lattice totals of mass, momentum and energy are conserved to rounding.
@@ -145,3 +147,62 @@ def test_4096_f16_fused_with_hinted_stores_equals_split():
         b.close()
         del fields
         torch.cuda.empty_cache()
+
+
+# The longest rows the library accepts. In AoS and CAoSoA a lattice row holds
+# all 37 populations interleaved, and a lane's in-row offset is a 32-bit byte
+# offset, so a row may span at most 4 GiB: ly * 37 * bytes <= 2^32 (clustered
+# rows also a whole number of 128-byte clusters). Longer rows are refused on
+# the host (tests/test_abi.py); these run one step at the limit itself.
+ELEM = {"f64": 8, "f32s": 4, "f16s": 2}
+
+
+def _longest_row(prec, layout):
+    eb = ELEM[prec]
+    ly = 2 ** 32 // (37 * eb)
+    if layout == "caosoa":
+        ly -= ly % (128 // eb)
+    return ly
+
+
+def _row_limit_sites(lx, ly, vl):
+    """Every row at both row ends (the largest offsets, and the periodic wrap
+    across them), the middle, and the seams between cluster lanes (in-row
+    positions k * LY/VL - 1 and k * LY/VL, whose clusters sit at the two ends
+    of the row's storage)."""
+    ys = {0, 1, 2, ly // 2, ly - 3, ly - 2, ly - 1}
+    if vl:
+        lyv = ly // vl
+        for k in (1, vl // 2, vl - 1):
+            ys |= {k * lyv - 1, k * lyv}
+    return sorted((x, y) for x in range(lx) for y in ys)
+
+
+@pytest.mark.parametrize("prec,layout,lx", [("f64", "caosoa", 4), ("f64", "aos", 2), ("f32s", "caosoa", 2),
+                                            ("f16s", "caosoa", 2)])
+def test_longest_accepted_row_sampled_parity(consts, prec, layout, lx):
+    """One fused step on lattices whose rows are the longest the host
+    accepts (14.5M FP64, 29M FP32 and 58M FP16 sites per row; 17-34 GB of
+    populations), sampled where the in-row offsets are largest, against the
+    oracle on each site's window. Random equilibrium: every neighbour
+    differs, so a wrong address cannot pass."""
+    ly = _longest_row(prec, layout)
+    step = 128 // ELEM[prec] if layout == "caosoa" else 1
+    assert lb.buffer_bytes(lx, ly, prec, layout) > 0
+    assert lb.buffer_bytes(lx, ly + step, prec, layout) == 0
+    n, tau = 1, 0.8
+    fields = inputs.random_equilibrium(lx, ly, seed=11)
+    sites = _row_limit_sites(lx, ly, 128 // ELEM[prec] if layout == "caosoa" else 0)
+    print(f"longest row {prec} {layout}: {lx} x {ly}, {len(sites)} sampled sites", flush=True)
+    with lb.Lattice(lx, ly, tau, fields, precision=prec, layout=layout) as lat:
+        lat.step(n)
+        got = _gather(lat, sites)
+    torch.cuda.empty_cache()
+    ref = lbm.run_window(fields, sites, n, tau)
+    w = consts["w"][None, :]
+    err = np.max(np.abs(got - ref) / w)
+    if prec == "f64":
+        assert err < 1e-13
+    else:
+        A = float(np.max(np.abs(ref - w) / w))
+        assert err <= (n + 1) * EPS[prec] * A * 4, (err, A)

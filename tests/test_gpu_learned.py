@@ -322,6 +322,24 @@ def test_learned_step_ragged_tiles(consts, oracle_net, lx, ly, layout):
     _check_sites(err, bar, FLOOR / TAU, what=f"ragged {lx}x{ly} {layout}")
 
 
+@pytest.mark.parametrize("layout,ly", [("caosoa", 29020032), ("aos", 29020049)])
+def test_learned_step_longest_accepted_row(consts, oracle_net, layout, ly):
+    """Rows of the longest length the host accepts for FP32 storage in the
+    interleaved layouts (ly * 37 * 4 bytes just under 4 GiB, the limit of the
+    kernel's 32-bit in-row offsets; a whole number of 32-site clusters in
+    CAoSoA): two rows, sampled at both row ends and at the cluster-lane
+    seams, where the offsets are largest. Random equilibrium, so every
+    neighbour differs."""
+    assert lb.buffer_bytes(2, ly, "f32s", layout) > 0
+    assert lb.buffer_bytes(2, ly + (32 if layout == "caosoa" else 1), "f32s", layout) == 0
+    ys = {0, 1, 2, ly // 2, ly - 3, ly - 2, ly - 1}
+    if layout == "caosoa":
+        ys |= {k * (ly // 32) + d for k in (1, 16, 31) for d in (-1, 0)}
+    sites = sorted((x, y) for x in range(2) for y in ys)
+    err, bar = _learned_sampled_parity(consts, oracle_net, 2, ly, layout, "random_equilibrium", sites)
+    _check_sites(err, bar, FLOOR / TAU, what=f"longest row {layout}")
+
+
 def _window_step(fields, site, collide):
     """One step at `site` on its 7 x 7 dependency window with a given collide."""
     rho, ux, uy, T = fields
