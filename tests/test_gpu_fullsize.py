@@ -4,6 +4,8 @@ benchmark times (2048 x 2048 and 8192 x 8192, CAoSoA layout, fused step).
 * Sampled parity: after n steps from the seeded state, sampled sites
   (random ones plus the corners and edges, where the periodic wrap acts) are
   compared with the oracle evaluated on each site's dependency window.
+* 16384 x 16384 in FP64 (the largest power-of-two lattice one GPU holds):
+  moments at sampled sites.
 * The longest rows the host accepts (in-row offsets at the 4 GiB limit of
   the kernels' 32-bit lane offsets), sampled the same way.
 * Properties after 1000 steps: the shear wave decays at the rate kinetic
@@ -206,3 +208,27 @@ def test_longest_accepted_row_sampled_parity(consts, prec, layout, lx):
     else:
         A = float(np.max(np.abs(ref - w) / w))
         assert err <= (n + 1) * EPS[prec] * A * 4, (err, A)
+
+
+@pytest.mark.parametrize("layout", ["caosoa", "soa"])
+def test_16384_f64_moments_at_sampled_sites(layout):
+    """The largest power-of-two FP64 lattice one GPU holds: 16384 x 16384,
+    two 79 GB population buffers (population and row terms of the element
+    index past 2^32). Two fused steps from a random equilibrium; the GPU's
+    FP64 moments at sampled sites against the moments of the oracle's state
+    on each site's window."""
+    L, n, tau = 16384, 2, 0.8
+    fields = inputs.random_equilibrium(L, L, seed=13)
+    sites = _sample_sites(L, L, 24, seed=8)
+    print(f"16384^2 f64 {layout}: {len(sites)} sampled sites", flush=True)
+    with lb.Lattice(L, L, tau, fields, precision="f64", layout=layout) as lat:
+        lat.step(n)
+        mom = lat.moments()
+        xs = torch.tensor([s[0] for s in sites], device=mom[0].device)
+        ys = torch.tensor([s[1] for s in sites], device=mom[0].device)
+        got = np.stack([m[xs, ys].cpu().numpy() for m in mom], axis=1)
+        del mom
+    torch.cuda.empty_cache()
+    ref = np.array([lbm.moments_site(f) for f in lbm.run_window(fields, sites, n, tau)])
+    err = np.max(np.abs(got - ref), axis=0)
+    assert np.all(err < 1e-12), err
