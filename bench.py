@@ -126,38 +126,53 @@ def _host_threads() -> int:
     return max(1, min(int(env), visible) if env.isdigit() and int(env) > 0 else visible)
 
 
-def _oracle_mlups(lbm, inputs, n: int, seconds_target: float):
+def _oracle_mlups(lbm, inputs, n: int, seconds_target: float, min_steps: int = 1):
     f = lbm.init(*inputs.shear_wave(n, n, seed=0))
     t0 = time.perf_counter()
     f = lbm.run(f, TAU, 1)
     one = time.perf_counter() - t0
-    steps = max(1, int(seconds_target / max(one, 1e-3)))
+    steps = max(min_steps, int(seconds_target / max(one, 1e-3)))
     t0 = time.perf_counter()
     lbm.run(f, TAU, steps)
     dt = time.perf_counter() - t0
     return n * n * steps / dt / 1e6, steps, dt
 
 
+def _oracle_config1(lbm, inputs):
+    """The 128 x 64 correctness workload in full: 100 steps from the random
+    equilibrium (seed 0)."""
+    f = lbm.init(*inputs.random_equilibrium(128, 64, seed=0))
+    t0 = time.perf_counter()
+    lbm.run(f, TAU, 100)
+    dt = time.perf_counter() - t0
+    return 128 * 64 * 100 / dt / 1e6, dt
+
+
 def cpu_baseline(seconds_target: float = 10.0):
-    """The FP64 oracle (plain C, the same source built once) on bounded samples
-    of the same workload, on the host's cores: one thread on a 512 x 512
-    window of the shear-wave state, and all the threads the process may use
-    (OpenMP over lattice columns) on a 1024 x 1024 window."""
+    """The FP64 oracle (plain C, the same source built once) on the host's
+    cores: all the threads the process may use (OpenMP over lattice columns)
+    on the 2048 x 2048 shear-wave workload for at least 10 steps (a
+    shortened run: the cost per step is constant), one thread on a 512 x 512
+    lattice of the same state, and the 128 x 64 workload in full on both."""
     from oracle import lbm
     from paper_1804_01918_amd import inputs
     nthreads = _host_threads()
     try:
         lbm.set_threads(1)
         m1, s1, t1 = _oracle_mlups(lbm, inputs, 512, seconds_target)
+        c1, ct1 = _oracle_config1(lbm, inputs)
         lbm.set_threads(nthreads)
-        mn, sn, tn = _oracle_mlups(lbm, inputs, 1024, seconds_target)
+        mn, sn, tn = _oracle_mlups(lbm, inputs, LX, seconds_target, min_steps=10)
+        cn, ctn = _oracle_config1(lbm, inputs)
     finally:
         lbm.set_threads(1)
     return {"value": mn, "unit": "MLUPS", "cores": nthreads, "kind": "oracle",
-            "sample": f"FP64 oracle, 1024x1024 shear-wave lattice, {sn} steps, {nthreads} threads "
-                      f"(OpenMP over columns), {tn:.1f} s",
+            "sample": f"FP64 oracle, {LX}x{LY} shear-wave lattice (the benchmark workload), {sn} of its 1000 "
+                      f"steps, {nthreads} threads (OpenMP over columns), {tn:.1f} s",
             "single_thread": {"value": m1, "unit": "MLUPS", "cores": 1,
                               "sample": f"FP64 oracle, 512x512 shear-wave lattice, {s1} steps, 1 thread, {t1:.1f} s"},
+            "config_128x64_100_steps": {"single_thread_mlups": c1, "single_thread_s": ct1,
+                                        "all_threads_mlups": cn, "all_threads_s": ctn},
             "cpu_model": _cpu_model(), "host_cpus_visible": len(os.sched_getaffinity(0))}
 
 
