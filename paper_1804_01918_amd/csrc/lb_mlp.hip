@@ -534,17 +534,20 @@ __global__ __launch_bounds__(TB) void k_mlp_update(float* __restrict__ params, f
     }
 }
 
-// The binary16 GELU of the inference form on x[0..n): two values per lane,
+// The binary16 GELU of the inference form on x[0..n): four values per lane,
 // through the same packed instructions as the hidden layers.
 __global__ __launch_bounds__(TB) void k_gelu16(const uint16_t* __restrict__ x, uint16_t* __restrict__ y, int64_t n)
 {
-    const int64_t i = 2 * ((int64_t)blockIdx.x * TB + threadIdx.x);
+    const int64_t i = 4 * ((int64_t)blockIdx.x * TB + threadIdx.x);
     if (i >= n) return;
-    const float a = (float)__builtin_bit_cast(_Float16, x[i]);
-    const float b = i + 1 < n ? (float)__builtin_bit_cast(_Float16, x[i + 1]) : 0.0f;
-    const uint32_t r = gelu_h2(a, b);
-    y[i] = (uint16_t)r;
-    if (i + 1 < n) y[i + 1] = (uint16_t)(r >> 16);
+    float v[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) v[j] = i + j < n ? (float)__builtin_bit_cast(_Float16, x[i + j]) : 0.0f;
+    uint32_t r[2];
+    gelu_h2x2(v[0], v[1], v[2], v[3], r[0], r[1]);
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+        if (i + j < n) y[i + j] = (uint16_t)(r[j >> 1] >> (16 * (j & 1)));
 }
 
 // Learned equilibrium of n shifted-population sites (one per lane), with the
@@ -1007,9 +1010,9 @@ int lb_mlp_gelu16(const uint16_t* x, uint16_t* y, int64_t n, void* stream)
 {
     if (!x || !y || n < 0) return mfail(nullptr, LB_EINVAL, "lb_mlp_gelu16: bad argument");
     if (n == 0) return LB_OK;
-    const int64_t pairs = (n + 1) / 2;
-    if (pairs > (int64_t)TB * 0x7fffffff) return mfail(nullptr, LB_EINVAL, "lb_mlp_gelu16: n is too large");
-    hipLaunchKernelGGL(k_gelu16, dim3((unsigned)((pairs + TB - 1) / TB)), dim3(TB), 0, (hipStream_t)stream, x, y, n);
+    const int64_t quads = (n + 3) / 4;  // four values per lane
+    if (quads > (int64_t)TB * 0x7fffffff) return mfail(nullptr, LB_EINVAL, "lb_mlp_gelu16: n is too large");
+    hipLaunchKernelGGL(k_gelu16, dim3((unsigned)((quads + TB - 1) / TB)), dim3(TB), 0, (hipStream_t)stream, x, y, n);
     return mcheck(nullptr, "lb_mlp_gelu16");
 }
 

@@ -97,7 +97,7 @@ __device__ inline f32x4 mfma(bf16x8 a, bf16x8 b, f32x4 c)
 }
 
 // Binary16 (IEEE half) tiles: v_mfma_f32_16x16x32_f16 has the BF16 lane
-// layout; the hidden layers of inference run on it (see gelu_h2).
+// layout; the hidden layers of inference run on it (see gelu_h2x2).
 typedef _Float16 f16x8 __attribute__((ext_vector_type(8)));
 typedef _Float16 f16x2 __attribute__((ext_vector_type(2)));
 typedef uint32_t u32x4v __attribute__((ext_vector_type(4)));
@@ -108,35 +108,44 @@ __device__ inline f32x4 mfma_f16(u32x4v a, u32x4v b, f32x4 c)
 }
 __host__ __device__ inline uint16_t f16_bits(float f) { return __builtin_bit_cast(uint16_t, (_Float16)f); }
 
-// GELU of two FP32 pre-activations in binary16 arithmetic, packed in one
-// word (a low, b high): every operation rounds to nearest even in binary16,
+// GELU of FP32 pre-activations in binary16 arithmetic, two pairs at a time,
+// (a, b) into r0 and (c, d) into r1, each pair packed in one word (first
+// value low): every operation rounds to nearest even in binary16,
 //   x = h(a), y = x (K1 x^2 + K2) (the K1 product and K2 sum fused), e = 2^y,
 //   r = 1 / (1 + e), result x r,
 // with K1, K2 of gelu_fast rounded to binary16. Packed instructions take
 // both halves at once; the hardware exponential and reciprocal of binary16
 // are correctly rounded (checked over every binary16 input), so the result
-// is a fixed function of (a, b) that a host can reproduce bit for bit. The
-// half-word results of the two transcendentals are written in place (SDWA):
-// the second write reads the first one's register, which needs one wait
-// state after a partial-register write on this GPU.
-__device__ inline uint32_t gelu_h2(float a, float b)
+// is a fixed function of the inputs that a host can reproduce bit for bit.
+// The half-word results of the transcendentals are written in place (SDWA):
+// the second write of a register reads the first one's result, which needs
+// one wait state after a partial-register write on this GPU; the writes of
+// the two pairs alternate, so each is the other's wait state.
+__device__ inline void gelu_h2x2(float a, float b, float c, float d, uint32_t& r0, uint32_t& r1)
 {
-    const f16x2 x = __builtin_convertvector((float __attribute__((ext_vector_type(2)))){a, b}, f16x2);
+    typedef float f32x2 __attribute__((ext_vector_type(2)));
+    const f16x2 x0 = __builtin_convertvector((f32x2){a, b}, f16x2);
+    const f16x2 x1 = __builtin_convertvector((f32x2){c, d}, f16x2);
     const f16x2 k1 = {(_Float16)GELU_K1, (_Float16)GELU_K1}, k2 = {(_Float16)GELU_K2, (_Float16)GELU_K2};
-    const f16x2 y = x * __builtin_elementwise_fma(k1, x * x, k2);
-    uint32_t e, r;
-    asm("v_exp_f16_sdwa %0, %1 dst_sel:WORD_0 dst_unused:UNUSED_PRESERVE src0_sel:WORD_0\n\t"
-        "s_nop 0\n\t"
-        "v_exp_f16_sdwa %0, %1 dst_sel:WORD_1 dst_unused:UNUSED_PRESERVE src0_sel:WORD_1"
-        : "=&v"(e)
-        : "v"(__builtin_bit_cast(uint32_t, y)));
-    const f16x2 d = __builtin_bit_cast(f16x2, e) + (f16x2){(_Float16)1, (_Float16)1};
-    asm("v_rcp_f16_sdwa %0, %1 dst_sel:WORD_0 dst_unused:UNUSED_PRESERVE src0_sel:WORD_0\n\t"
-        "s_nop 0\n\t"
-        "v_rcp_f16_sdwa %0, %1 dst_sel:WORD_1 dst_unused:UNUSED_PRESERVE src0_sel:WORD_1"
-        : "=&v"(r)
-        : "v"(__builtin_bit_cast(uint32_t, d)));
-    return __builtin_bit_cast(uint32_t, x * __builtin_bit_cast(f16x2, r));
+    const f16x2 y0 = x0 * __builtin_elementwise_fma(k1, x0 * x0, k2);
+    const f16x2 y1 = x1 * __builtin_elementwise_fma(k1, x1 * x1, k2);
+    uint32_t e0, e1, q0, q1;
+    asm("v_exp_f16_sdwa %0, %2 dst_sel:WORD_0 dst_unused:UNUSED_PRESERVE src0_sel:WORD_0\n\t"
+        "v_exp_f16_sdwa %1, %3 dst_sel:WORD_0 dst_unused:UNUSED_PRESERVE src0_sel:WORD_0\n\t"
+        "v_exp_f16_sdwa %0, %2 dst_sel:WORD_1 dst_unused:UNUSED_PRESERVE src0_sel:WORD_1\n\t"
+        "v_exp_f16_sdwa %1, %3 dst_sel:WORD_1 dst_unused:UNUSED_PRESERVE src0_sel:WORD_1"
+        : "=&v"(e0), "=&v"(e1)
+        : "v"(__builtin_bit_cast(uint32_t, y0)), "v"(__builtin_bit_cast(uint32_t, y1)));
+    const f16x2 one = {(_Float16)1, (_Float16)1};
+    const f16x2 d0 = __builtin_bit_cast(f16x2, e0) + one, d1 = __builtin_bit_cast(f16x2, e1) + one;
+    asm("v_rcp_f16_sdwa %0, %2 dst_sel:WORD_0 dst_unused:UNUSED_PRESERVE src0_sel:WORD_0\n\t"
+        "v_rcp_f16_sdwa %1, %3 dst_sel:WORD_0 dst_unused:UNUSED_PRESERVE src0_sel:WORD_0\n\t"
+        "v_rcp_f16_sdwa %0, %2 dst_sel:WORD_1 dst_unused:UNUSED_PRESERVE src0_sel:WORD_1\n\t"
+        "v_rcp_f16_sdwa %1, %3 dst_sel:WORD_1 dst_unused:UNUSED_PRESERVE src0_sel:WORD_1"
+        : "=&v"(q0), "=&v"(q1)
+        : "v"(__builtin_bit_cast(uint32_t, d0)), "v"(__builtin_bit_cast(uint32_t, d1)));
+    r0 = __builtin_bit_cast(uint32_t, x0 * __builtin_bit_cast(f16x2, q0));
+    r1 = __builtin_bit_cast(uint32_t, x1 * __builtin_bit_cast(f16x2, q1));
 }
 
 // FP8 (e4m3, the OCP variant without infinities) tiles:

@@ -184,8 +184,10 @@ __device__ inline void network_outputs(const Net& net, uint16_t* X)
                         hq[mt >> 1][nt][mt & 1] = pack_fp8<true>(gelu16(a[b][nt][2]), gelu16(a[b][nt][3]), v);
                         asm volatile("" : "+v"(hq[mt >> 1][nt][mt & 1]));
                     } else {
-                        hh[mt >> 1][nt][2 * (mt & 1)] = gelu_h2(a[b][nt][0], a[b][nt][1]);
-                        hh[mt >> 1][nt][2 * (mt & 1) + 1] = gelu_h2(a[b][nt][2], a[b][nt][3]);
+                        uint32_t r0, r1;
+                        gelu_h2x2(a[b][nt][0], a[b][nt][1], a[b][nt][2], a[b][nt][3], r0, r1);
+                        hh[mt >> 1][nt][2 * (mt & 1)] = r0;
+                        hh[mt >> 1][nt][2 * (mt & 1) + 1] = r1;
                         asm volatile("" : "+v"(hh[mt >> 1][nt]));
                     }
                 }
@@ -244,11 +246,17 @@ __device__ inline void network_outputs(const Net& net, uint16_t* X)
                 const int b = mt & 1;
 #pragma unroll
                 for (int nt = 0; nt < 2; ++nt) {
+                    if constexpr (FP8) {
 #pragma unroll
-                    for (int j = 0; j < 2; ++j) {
-                        const float lo = a[b][nt][2 * j], hi = a[b][nt][2 * j + 1];
-                        h2[nt][2 * (mt & 1) + j] = FP8 ? pack_bf16(gelu_k(lo, k1, k2), gelu_k(hi, k1, k2))
-                                                       : gelu_h2(lo, hi);
+                        for (int j = 0; j < 2; ++j) {
+                            const float lo = a[b][nt][2 * j], hi = a[b][nt][2 * j + 1];
+                            h2[nt][2 * (mt & 1) + j] = pack_bf16(gelu_k(lo, k1, k2), gelu_k(hi, k1, k2));
+                        }
+                    } else {
+                        uint32_t r0, r1;
+                        gelu_h2x2(a[b][nt][0], a[b][nt][1], a[b][nt][2], a[b][nt][3], r0, r1);
+                        h2[nt][2 * (mt & 1)] = r0;
+                        h2[nt][2 * (mt & 1) + 1] = r1;
                     }
                 }
                 if (mt & 1) {
