@@ -159,7 +159,7 @@ __device__ inline void learned_tiles(LearnedLds& S, const mlp::Net& gnet, const 
             for (int p = 0; p < Q; ++p) in[p] = P::template load<false>(at(p), p);
             mlp::stage_inputs(X, net, in);
         }
-        mlp::network_outputs<FP8>(net, X);
+        mlp::network_outputs<FP8, true>(net, X);
         // second gather: the populations for projection and relaxation
         float v[Q];
 #pragma unroll

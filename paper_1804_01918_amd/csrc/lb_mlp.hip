@@ -534,19 +534,19 @@ __global__ __launch_bounds__(TB) void k_mlp_update(float* __restrict__ params, f
     }
 }
 
-// The binary16 GELU of the inference form on x[0..n): four values per lane,
+// The binary16 GELU of the inference form on x[0..n): eight values per lane,
 // through the same packed instructions as the hidden layers.
 __global__ __launch_bounds__(TB) void k_gelu16(const uint16_t* __restrict__ x, uint16_t* __restrict__ y, int64_t n)
 {
-    const int64_t i = 4 * ((int64_t)blockIdx.x * TB + threadIdx.x);
+    const int64_t i = 8 * ((int64_t)blockIdx.x * TB + threadIdx.x);
     if (i >= n) return;
-    float v[4];
+    float v[8];
 #pragma unroll
-    for (int j = 0; j < 4; ++j) v[j] = i + j < n ? (float)__builtin_bit_cast(_Float16, x[i + j]) : 0.0f;
-    uint32_t r[2];
-    gelu_h2x2(v[0], v[1], v[2], v[3], r[0], r[1]);
+    for (int j = 0; j < 8; ++j) v[j] = i + j < n ? (float)__builtin_bit_cast(_Float16, x[i + j]) : 0.0f;
+    uint32_t r[4];
+    gelu_h2x4(v, r);
 #pragma unroll
-    for (int j = 0; j < 4; ++j)
+    for (int j = 0; j < 8; ++j)
         if (i + j < n) y[i + j] = (uint16_t)(r[j >> 1] >> (16 * (j & 1)));
 }
 
@@ -567,7 +567,7 @@ __global__ __launch_bounds__(TB) __attribute__((amdgpu_waves_per_eu(2, 2))) void
         for (int p = 0; p < Q; ++p) in[p] = active ? pre[s * Q + p] : 0.0f;
         stage_inputs(X, net, in);
     }
-    network_outputs<FP8>(net, X);
+    network_outputs<FP8, false>(net, X);
     float g[Q];
 #pragma unroll
     for (int p = 0; p < Q; ++p) g[p] = active ? pre[s * Q + p] : 0.0f;
@@ -1010,9 +1010,9 @@ int lb_mlp_gelu16(const uint16_t* x, uint16_t* y, int64_t n, void* stream)
 {
     if (!x || !y || n < 0) return mfail(nullptr, LB_EINVAL, "lb_mlp_gelu16: bad argument");
     if (n == 0) return LB_OK;
-    const int64_t quads = (n + 3) / 4;  // four values per lane
-    if (quads > (int64_t)TB * 0x7fffffff) return mfail(nullptr, LB_EINVAL, "lb_mlp_gelu16: n is too large");
-    hipLaunchKernelGGL(k_gelu16, dim3((unsigned)((quads + TB - 1) / TB)), dim3(TB), 0, (hipStream_t)stream, x, y, n);
+    const int64_t lanes = (n + 7) / 8;  // eight values per lane
+    if (lanes > (int64_t)TB * 0x7fffffff) return mfail(nullptr, LB_EINVAL, "lb_mlp_gelu16: n is too large");
+    hipLaunchKernelGGL(k_gelu16, dim3((unsigned)((lanes + TB - 1) / TB)), dim3(TB), 0, (hipStream_t)stream, x, y, n);
     return mcheck(nullptr, "lb_mlp_gelu16");
 }
 

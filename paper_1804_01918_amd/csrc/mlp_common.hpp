@@ -148,6 +148,39 @@ __device__ inline void gelu_h2x2(float a, float b, float c, float d, uint32_t& r
     r1 = __builtin_bit_cast(uint32_t, x1 * __builtin_bit_cast(f16x2, q1));
 }
 
+// gelu_h2x2 of four pairs, v[2i], v[2i + 1] into r[i].
+__device__ inline void gelu_h2x4(const float (&v)[8], uint32_t (&r)[4])
+{
+    typedef float f32x2 __attribute__((ext_vector_type(2)));
+    const f16x2 k1 = {(_Float16)GELU_K1, (_Float16)GELU_K1}, k2 = {(_Float16)GELU_K2, (_Float16)GELU_K2};
+    f16x2 x[4];
+    uint32_t y[4], e[4], dd[4], q[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        x[i] = __builtin_convertvector((f32x2){v[2 * i], v[2 * i + 1]}, f16x2);
+        y[i] = __builtin_bit_cast(uint32_t, x[i] * __builtin_elementwise_fma(k1, x[i] * x[i], k2));
+    }
+#define D2Q37_TRANS4(OP, D, S)                                                                  \
+    asm(OP " %0, %4 dst_sel:WORD_0 dst_unused:UNUSED_PRESERVE src0_sel:WORD_0\n\t"             \
+        OP " %1, %5 dst_sel:WORD_0 dst_unused:UNUSED_PRESERVE src0_sel:WORD_0\n\t"             \
+        OP " %2, %6 dst_sel:WORD_0 dst_unused:UNUSED_PRESERVE src0_sel:WORD_0\n\t"             \
+        OP " %3, %7 dst_sel:WORD_0 dst_unused:UNUSED_PRESERVE src0_sel:WORD_0\n\t"             \
+        OP " %0, %4 dst_sel:WORD_1 dst_unused:UNUSED_PRESERVE src0_sel:WORD_1\n\t"             \
+        OP " %1, %5 dst_sel:WORD_1 dst_unused:UNUSED_PRESERVE src0_sel:WORD_1\n\t"             \
+        OP " %2, %6 dst_sel:WORD_1 dst_unused:UNUSED_PRESERVE src0_sel:WORD_1\n\t"             \
+        OP " %3, %7 dst_sel:WORD_1 dst_unused:UNUSED_PRESERVE src0_sel:WORD_1"                  \
+        : "=&v"(D[0]), "=&v"(D[1]), "=&v"(D[2]), "=&v"(D[3])                                   \
+        : "v"(S[0]), "v"(S[1]), "v"(S[2]), "v"(S[3]))
+    D2Q37_TRANS4("v_exp_f16_sdwa", e, y);
+    const f16x2 one = {(_Float16)1, (_Float16)1};
+#pragma unroll
+    for (int i = 0; i < 4; ++i) dd[i] = __builtin_bit_cast(uint32_t, __builtin_bit_cast(f16x2, e[i]) + one);
+    D2Q37_TRANS4("v_rcp_f16_sdwa", q, dd);
+#undef D2Q37_TRANS4
+#pragma unroll
+    for (int i = 0; i < 4; ++i) r[i] = __builtin_bit_cast(uint32_t, x[i] * __builtin_bit_cast(f16x2, q[i]));
+}
+
 // FP8 (e4m3, the OCP variant without infinities) tiles:
 // v_mfma_f32_16x16x32_fp8_fp8 has the lane layout above with eight one-byte
 // values per lane (one 64-bit register pair per operand).
@@ -223,7 +256,7 @@ struct Net {
     const float* gk2 = nullptr;
     int ldq = HID;        // row stride of W2q in bytes
     // LDS copies of the biases of the form in use (set by share_weights;
-    // null: read them from params, or b1s / b2s in the FP8 form)
+    // otherwise they are read from params, or b1s / b2s in the FP8 form)
     const float* lb1 = nullptr;
     const float* lb2 = nullptr;
     const float* lb3 = nullptr;

@@ -123,13 +123,15 @@ __device__ inline float gelu_k(float a, float k1, float k2)
 // runs in the same order as a layer-at-a-time evaluation (bias first, then
 // k blocks in increasing order), so the results do not depend on this
 // schedule.
-template <bool FP8>
+template <bool FP8, bool SHARED>
 __device__ inline void network_outputs(const Net& net, uint16_t* X)
 {
     const int lane = lane_id(), col = lane & 15, quad = lane >> 4;
-    const float* b1 = net.lb1 ? net.lb1 : FP8 ? net.b1s : net.params + OFF_B1;
-    const float* b2 = net.lb2 ? net.lb2 : FP8 ? net.b2s : net.params + OFF_B2;
-    const float* b3 = net.lb3 ? net.lb3 : net.params + OFF_B3;
+    // SHARED: `net` is share_weights' view, biases in LDS (known at compile
+    // time, so their reads are LDS reads, not generic ones)
+    const float* b1 = SHARED ? net.lb1 : FP8 ? net.b1s : net.params + OFF_B1;
+    const float* b2 = SHARED ? net.lb2 : FP8 ? net.b2s : net.params + OFF_B2;
+    const float* b3 = SHARED ? net.lb3 : net.params + OFF_B3;
     const uint16_t* W1 = FP8 ? net.W1s : net.W1b;
     const uint16_t* W3 = FP8 ? net.W3s : net.W3p;
     float k1 = GELU_K1, k2 = GELU_K2;
@@ -177,17 +179,22 @@ __device__ inline void network_outputs(const Net& net, uint16_t* X)
             // nothing else consumes them before the hidden layer)
             auto act = [&](int mt) {
                 const int b = mt & 1;
+                if constexpr (FP8) {
 #pragma unroll
-                for (int nt = 0; nt < 2; ++nt) {
-                    if constexpr (FP8) {
+                    for (int nt = 0; nt < 2; ++nt) {
                         const uint32_t v = pack_fp8<false>(gelu16(a[b][nt][0]), gelu16(a[b][nt][1]), 0u);
                         hq[mt >> 1][nt][mt & 1] = pack_fp8<true>(gelu16(a[b][nt][2]), gelu16(a[b][nt][3]), v);
                         asm volatile("" : "+v"(hq[mt >> 1][nt][mt & 1]));
-                    } else {
-                        uint32_t r0, r1;
-                        gelu_h2x2(a[b][nt][0], a[b][nt][1], a[b][nt][2], a[b][nt][3], r0, r1);
-                        hh[mt >> 1][nt][2 * (mt & 1)] = r0;
-                        hh[mt >> 1][nt][2 * (mt & 1) + 1] = r1;
+                    }
+                } else {
+                    const float v[8] = {a[b][0][0], a[b][0][1], a[b][0][2], a[b][0][3],
+                                        a[b][1][0], a[b][1][1], a[b][1][2], a[b][1][3]};
+                    uint32_t r[4];
+                    gelu_h2x4(v, r);
+#pragma unroll
+                    for (int nt = 0; nt < 2; ++nt) {
+                        hh[mt >> 1][nt][2 * (mt & 1)] = r[2 * nt];
+                        hh[mt >> 1][nt][2 * (mt & 1) + 1] = r[2 * nt + 1];
                         asm volatile("" : "+v"(hh[mt >> 1][nt]));
                     }
                 }
@@ -244,19 +251,23 @@ __device__ inline void network_outputs(const Net& net, uint16_t* X)
             };
             auto act = [&](int mt) {
                 const int b = mt & 1;
+                if constexpr (FP8) {
 #pragma unroll
-                for (int nt = 0; nt < 2; ++nt) {
-                    if constexpr (FP8) {
+                    for (int nt = 0; nt < 2; ++nt)
 #pragma unroll
                         for (int j = 0; j < 2; ++j) {
                             const float lo = a[b][nt][2 * j], hi = a[b][nt][2 * j + 1];
                             h2[nt][2 * (mt & 1) + j] = pack_bf16(gelu_k(lo, k1, k2), gelu_k(hi, k1, k2));
                         }
-                    } else {
-                        uint32_t r0, r1;
-                        gelu_h2x2(a[b][nt][0], a[b][nt][1], a[b][nt][2], a[b][nt][3], r0, r1);
-                        h2[nt][2 * (mt & 1)] = r0;
-                        h2[nt][2 * (mt & 1) + 1] = r1;
+                } else {
+                    const float v[8] = {a[b][0][0], a[b][0][1], a[b][0][2], a[b][0][3],
+                                        a[b][1][0], a[b][1][1], a[b][1][2], a[b][1][3]};
+                    uint32_t r[4];
+                    gelu_h2x4(v, r);
+#pragma unroll
+                    for (int nt = 0; nt < 2; ++nt) {
+                        h2[nt][2 * (mt & 1)] = r[2 * nt];
+                        h2[nt][2 * (mt & 1) + 1] = r[2 * nt + 1];
                     }
                 }
                 if (mt & 1) {
