@@ -631,6 +631,28 @@ def test_gelu16_matches_oracle_on_every_binary16_input():
     assert np.array_equal(odd, got[:7])
 
 
+@pytest.mark.parametrize("n", [1, 2, 7, 8, 9, 15, 17, 2051])
+def test_gelu16_ragged_counts_write_only_their_outputs(n):
+    """Counts that leave a lane partly filled (eight values per lane): the
+    first n outputs equal those of the full evaluation, and the output
+    words past n keep their poison."""
+    rng = np.random.default_rng(n)
+    bits = rng.integers(0, 0x7C00, size=n, dtype=np.uint16)  # finite, non-negative
+    bits[::3] |= 0x8000  # and some negative
+    want = lb.gelu16(torch.from_numpy(bits.view(np.int16).copy()).cuda()).cpu().numpy().view(np.uint16)
+    x = torch.from_numpy(np.concatenate([bits, np.zeros(16, np.uint16)]).view(np.int16)).cuda()
+    y = torch.full((n + 16,), 0x5A5A, dtype=torch.int16, device="cuda")
+    torch.cuda.synchronize()
+    assert lb.lib().lb_mlp_gelu16(x.data_ptr(), y.data_ptr(), n, None) == lb.LB_OK
+    torch.cuda.synchronize()
+    out = y.cpu().numpy().view(np.uint16)
+    assert np.array_equal(out[:n], want)
+    assert np.all(out[n:] == 0x5A5A)
+    with np.errstate(invalid="ignore"):
+        ref = S.gelu_f16(bits.view(np.float16).astype(np.float64)).astype(np.float16).view(np.uint16)
+    assert np.array_equal(out[:n], ref)
+
+
 def test_binary16_overflow_falls_back_without_leaking(consts, oracle_net):
     """Sites whose moments lie inside the training box but whose populations
     are far from equilibrium (a moment-free perturbation of 3e4 w_p) drive
