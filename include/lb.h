@@ -118,7 +118,10 @@ size_t lb_buffer_bytes(int32_t lx, int32_t ly, int32_t precision, int32_t layout
 /* Bytes of scratch a context of this lattice needs: the FP64 partial sums of
  * the audit (4 per 256-site row tile), its 4 totals, the two counters of
  * the learned collide, the walls' equilibrium table and their per-column
- * densities (2 * lx); 0 for an invalid extent. Host only. */
+ * densities (2 * lx), then the learned collide's fallback ring (the pulled
+ * populations of sites waiting for the plain collide: 160 KB for each
+ * workgroup of its persistent grid, min(lx * ceil(ly / 512), 256) of
+ * them); 0 for an invalid extent. Host only. */
 size_t lb_scratch_bytes(int32_t lx, int32_t ly);
 
 /* Create a context and set the populations of buf[0] to the equilibrium of

@@ -31,12 +31,14 @@ struct lb_ctx {
     const lb_mlp* mlp;     // learned collide, or NULL for the plain one
     float threshold;       // residual above which a site falls back
     Geo lgeo;              // geometry of the learned kernels (512-site tiles)
-    int lgrid;             // their persistent grid: min(tiles, compute units)
+    int lgrid;             // their persistent grid: min(tiles, compute units, ring_wgs)
     int64_t audit_parts;   // partial sums written by the last fused audit
     bool fused_audit_valid;
     bool forced;           // nonzero body force: the collides' FORCE path
     double force[3];       // R tau gx, R tau gy, tau (1 - tau) |g|^2 / 2
     double* wall_tab;      // scratch: [2][WALL_TAB] (walls only)
+    float* ring;           // scratch: fallback ring of the learned kernels, RING_WG_BYTES per workgroup
+    int ring_wgs;          // workgroups it holds slots for
     int device;            // device current at lb_init (where the buffers live)
     void* static_scratch;  // that device's address of `scratch` (lb_audit_static), or NULL
     bool f16_stream_stores;  // FP16 buffers of at least STREAM_STORE_BYTES: hinted stores in lb_step
@@ -104,6 +106,18 @@ bool row_bytes_ok(int32_t ly, int eb, int layout)
 {
     const uint64_t per = (layout == LB_AOS || layout == LB_CAOSOA) ? (uint64_t)Q * eb : (uint64_t)eb;
     return (uint64_t)ly * per <= ((uint64_t)1 << 32);
+}
+
+// Scratch before the fallback ring (see lb_scratch_bytes), a multiple of 256.
+size_t base_scratch_bytes(int32_t lx, int32_t ly)
+{
+    return round256((size_t)((int64_t)lx * div_up(ly, BLOCK) * 4 + 4 + 2 + 2 * WALL_TAB) * sizeof(double));
+}
+// Workgroups of the learned kernels' persistent grid the ring holds slots
+// for: one per 512-site tile, at most LRING_WGS.
+int ring_wgs_of(int32_t lx, int32_t ly)
+{
+    return (int)std::min<int64_t>((int64_t)lx * div_up(ly, LBLOCK), LRING_WGS);
 }
 
 // Calls f(P{}, L{}) for the runtime precision and layout.
@@ -245,8 +259,9 @@ size_t lb_scratch_bytes(int32_t lx, int32_t ly)
     const int64_t n = (int64_t)lx * ly;
     if (n >= ((int64_t)1 << 31)) return 0;
     // one partial sum of 4 doubles per row-tiled workgroup, the 4 totals, two
-    // 64-bit counters of the learned collide and the walls' table
-    return round256((size_t)((int64_t)lx * div_up(ly, BLOCK) * 4 + 4 + 2 + 2 * WALL_TAB) * sizeof(double));
+    // 64-bit counters of the learned collide and the walls' table; then the
+    // learned kernels' fallback ring
+    return base_scratch_bytes(lx, ly) + (size_t)ring_wgs_of(lx, ly) * RING_WG_BYTES;
 }
 
 int lb_init(lb_ctx** out, const lb_config* cfg, const double* rho, const double* ux, const double* uy,
@@ -304,6 +319,8 @@ int lb_init(lb_ctx** out, const lb_config* cfg, const double* rho, const double*
     c->totals = c->partials + 4 * c->nblocks;
     c->counts = (unsigned long long*)(c->totals + 4);
     c->wall_tab = c->totals + 4 + 2;
+    c->ring = (float*)((char*)k.scratch + base_scratch_bytes(k.lx, k.ly));
+    c->ring_wgs = ring_wgs_of(k.lx, k.ly);
     c->forced = k.gx != 0.0 || k.gy != 0.0;
     c->force[0] = R * k.tau * k.gx;
     c->force[1] = R * k.tau * k.gy;
@@ -374,7 +391,7 @@ int lb_collide(lb_ctx* c)
             using L = decltype(l);
 #define D2Q37_LCOLL(CMP, F8)                                                                                       \
     hipLaunchKernelGGL((k_collide_learned<L, CMP, F8>), lgrid_of(c), dim3(LBLOCK), 0, c->stream, (float*)cur_buf(c), \
-                       c->lgeo, omega, c->mlp->net(), c->threshold, c->counts)
+                       c->lgeo, omega, c->mlp->net(), c->threshold, c->counts, c->ring)
             if (comp) {
                 if (fp8) D2Q37_LCOLL(true, true); else D2Q37_LCOLL(true, false);
             } else {
@@ -425,7 +442,7 @@ int lb_step(lb_ctx* c, int32_t nsteps)
                 const bool fp8 = c->mlp->precision == LB_MLP_FP8;
 #define D2Q37_LSTEP(CMP, AUD, F8)                                                                                  \
     hipLaunchKernelGGL((k_step_learned<L, CMP, AUD, F8>), lgrid_of(c), dim3(LBLOCK), 0, c->stream, src, dst, c->lgeo, \
-                       omega, c->mlp->net(), c->threshold, c->partials, c->counts)
+                       omega, c->mlp->net(), c->threshold, c->partials, c->counts, c->ring)
 #define D2Q37_LSTEP8(CMP, AUD) \
     do { if (fp8) D2Q37_LSTEP(CMP, AUD, true); else D2Q37_LSTEP(CMP, AUD, false); } while (0)
                 if (comp) {
@@ -571,7 +588,8 @@ int lb_set_surrogate(lb_ctx* c, const lb_mlp* m, double threshold)
     c->lgeo = c->geo;
     c->lgeo.tpr = (int)div_up(c->geo.ly, LBLOCK);
     const int64_t tiles = (int64_t)c->geo.lx * c->lgeo.tpr;
-    c->lgrid = (int)std::min<int64_t>(tiles, ncu);
+    // one workgroup per compute unit, and no more than the ring has slots for
+    c->lgrid = (int)std::min<int64_t>(std::min<int64_t>(tiles, ncu), c->ring_wgs);
     c->mlp = m;
     c->threshold = (float)threshold;
     return LB_OK;

@@ -9,8 +9,12 @@
 // stages its 64 sites' inputs in its own LDS rows, runs the network, then
 // gathers the populations a second time (cache hits) for the projection,
 // the fallback verdict and the relaxation. Sites that fall back are queued
-// per wavefront in LDS and collided 64 at a time with the plain FP32 collide,
-// so that a few fallback lanes do not hold a whole wavefront in it.
+// per wavefront and collided 64 at a time with the plain FP32 collide, so
+// that a few fallback lanes do not hold a whole wavefront in it: the site
+// index goes to LDS, the site's pulled populations (in registers at that
+// point) to the wavefront's slots of a ring in the caller's scratch, so that
+// a batch reads 64 compact slots instead of gathering again from 37 lines
+// per site.
 #pragma once
 
 #include "lb_kernels.hpp"
@@ -21,7 +25,10 @@ namespace d2q37 {
 constexpr int LBLOCK = 512;
 constexpr int LWAVES = LBLOCK / 64;
 
-constexpr int FQ = 128;  // fallback queue of a wavefront: < 64 waiting + one tile's 64
+constexpr int FQ = 128;  // fallback queue of a wavefront (circular): < 64 waiting + one tile's 64
+constexpr int RS = 40;   // floats per ring slot: the 37 populations, padded to 160 bytes
+constexpr int LRING_WGS = 256;  // workgroups the ring holds slots for (the persistent grid's cap)
+constexpr size_t RING_WG_BYTES = (size_t)LWAVES * FQ * RS * sizeof(float);
 
 struct LearnedLds {
     mlp::SharedWeights w;
@@ -31,25 +38,34 @@ struct LearnedLds {
 };
 static_assert(sizeof(LearnedLds) <= 160 * 1024, "the learned kernels' LDS must fit one compute unit");
 
-// Plain FP32 collide of the queued fallback sites q[0..n), n <= 64, one per
-// lane: populations gathered from src (pulled, or the site's own with
-// INPLACE), result stored at the site in dst. Every lane must call it.
-template <class L, bool COMP, bool AUDIT, bool INPLACE>
-__device__ inline void fallback_batch(const uint32_t* q, int n, const float* src, float* dst, const Geo& g, float om,
-                                      double (&acc)[4])
+// Plain FP32 collide of the n <= 64 queued fallback sites from queue position
+// h on, one per lane: populations read from their ring slots, result stored
+// at the site in dst. Every lane must call it, after the ring writes are
+// visible (fence_ring).
+template <class L, bool COMP, bool AUDIT>
+__device__ inline void fallback_batch(const uint32_t* q, const float* ring, int h, int n, float* dst, const Geo& g,
+                                      float om, double (&acc)[4])
 {
     using P = PrecF32S;
     constexpr int VL = vl_of<P>();
     const int lane = mlp::lane_id();
     const bool valid = lane < n;
-    const uint32_t e = q[valid ? lane : 0];
+    const int slot = (h + (valid ? lane : 0)) & (FQ - 1);
+    const uint32_t e = q[slot];
     const int fx = (int)(e / (uint32_t)g.ly), fr = (int)(e - (uint32_t)fx * (uint32_t)g.ly);
     Stencil<L, float, VL> st;
     st.setup(fx, fr, g);
+    const float* sp = ring + slot * RS;
     float v[Q];
 #pragma unroll
-    for (int p = 0; p < Q; ++p)
-        v[p] = P::template load<L::stream_loads>(INPLACE ? st.own(src, p, g) : st.src(src, p, g), p);
+    for (int j = 0; j < Q / 4; ++j) {
+        const float4 t = ((const float4*)sp)[j];
+        v[4 * j] = t.x;
+        v[4 * j + 1] = t.y;
+        v[4 * j + 2] = t.z;
+        v[4 * j + 3] = t.w;
+    }
+    v[Q - 1] = sp[Q - 1];
     if (valid) {
         double d[Q];
         collide_site<P, COMP>(v, om, [&](int p, float res) {
@@ -60,23 +76,39 @@ __device__ inline void fallback_batch(const uint32_t* q, int n, const float* src
     }
 }
 
-// Queue this tile's fallback lanes (mask m of lanes with fb set) and, once 64
-// are waiting, collide them. qn: entries waiting (wavefront-uniform).
-template <class L, bool COMP, bool AUDIT, bool INPLACE>
-__device__ inline void queue_fallback(uint32_t* q, int& qn, uint64_t m, bool fb, uint32_t site, const float* src,
-                                      float* dst, const Geo& g, float om, double (&acc)[4])
+// The wavefront's ring writes complete and visible to its own later reads
+// (other lanes read them).
+__device__ inline void fence_ring()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+}
+
+// Queue this tile's fallback lanes (mask m of lanes with fb set; v: the
+// lane's pulled populations) behind the qn entries waiting from position h,
+// and, once 64 are waiting, collide the oldest 64. h, qn: wavefront-uniform.
+template <class L, bool COMP, bool AUDIT>
+__device__ inline void queue_fallback(uint32_t* q, float* ring, int& h, int& qn, uint64_t m, bool fb, uint32_t site,
+                                      const float (&v)[Q], float* dst, const Geo& g, float om, double (&acc)[4])
 {
     if (m == 0) return;
     const int lane = mlp::lane_id();
-    if (fb) q[qn + __popcll(m & ((1ull << lane) - 1ull))] = site;
+    if (fb) {
+        const int slot = (h + qn + __popcll(m & ((1ull << lane) - 1ull))) & (FQ - 1);
+        q[slot] = site;
+        float* sp = ring + slot * RS;
+#pragma unroll
+        for (int j = 0; j < Q / 4; ++j)
+            ((float4*)sp)[j] = float4{v[4 * j], v[4 * j + 1], v[4 * j + 2], v[4 * j + 3]};
+        sp[Q - 1] = v[Q - 1];
+    }
     qn += __popcll(m);
     if (qn >= 64) {
         mlp::wave_sync();
-        fallback_batch<L, COMP, AUDIT, INPLACE>(q, 64, src, dst, g, om, acc);
-        const int rest = qn - 64;
-        mlp::wave_sync();
-        if (lane < rest) q[lane] = q[64 + lane];
-        qn = rest;
+        fence_ring();
+        fallback_batch<L, COMP, AUDIT>(q, ring, h, 64, dst, g, om, acc);
+        h = (h + 64) & (FQ - 1);
+        qn -= 64;
     }
 }
 
@@ -131,7 +163,8 @@ __device__ inline void finish_learned(LearnedLds& S, double (&acc)[4], unsigned 
 // partials[4 * blockIdx.x ..] receive the workgroup's FP64 sums.
 template <class L, bool COMP, bool AUDIT, bool INPLACE, bool FP8>
 __device__ inline void learned_tiles(LearnedLds& S, const mlp::Net& gnet, const float* src, float* dst, const Geo& g,
-                                     float om, float threshold, double* partials, unsigned long long* counts)
+                                     float om, float threshold, double* partials, unsigned long long* counts,
+                                     float* ring_all)
 {
     using P = PrecF32S;
     constexpr int VL = vl_of<P>();
@@ -139,7 +172,8 @@ __device__ inline void learned_tiles(LearnedLds& S, const mlp::Net& gnet, const 
     __syncthreads();
     uint16_t* X = S.X[threadIdx.x >> 6];
     uint32_t* q = S.fq[threadIdx.x >> 6];
-    int qn = 0;
+    float* ring = ring_all + ((size_t)blockIdx.x * LWAVES + (threadIdx.x >> 6)) * (FQ * RS);
+    int qh = 0, qn = 0;
     double acc[4] = {0.0, 0.0, 0.0, 0.0};
     unsigned long long nfb = 0, nact = 0;
     const TileWalk tw = tile_walk((int64_t)g.lx * g.tpr);
@@ -182,11 +216,15 @@ __device__ inline void learned_tiles(LearnedLds& S, const mlp::Net& gnet, const 
         nact += __popcll(__ballot(active));
         // in place, a queued site stays untouched until its batch runs:
         // every site writes only itself
-        queue_fallback<L, COMP, AUDIT, INPLACE>(q, qn, m, fb, (uint32_t)xrow * (uint32_t)g.ly + (uint32_t)r, src, dst,
-                                                g, om, acc);
+        queue_fallback<L, COMP, AUDIT>(q, ring, qh, qn, m, fb, (uint32_t)xrow * (uint32_t)g.ly + (uint32_t)r, v, dst,
+                                       g, om, acc);
         mlp::wave_sync();  // the staged rows are reused by the next tile
     }
-    if (qn > 0) fallback_batch<L, COMP, AUDIT, INPLACE>(q, qn, src, dst, g, om, acc);
+    if (qn > 0) {
+        mlp::wave_sync();
+        fence_ring();
+        fallback_batch<L, COMP, AUDIT>(q, ring, qh, qn, dst, g, om, acc);
+    }
     finish_learned<AUDIT>(S, acc, nfb, nact, partials, counts);
 }
 
@@ -195,20 +233,20 @@ __device__ inline void learned_tiles(LearnedLds& S, const mlp::Net& gnet, const 
 template <class L, bool COMP, bool AUDIT, bool FP8>
 __global__ __launch_bounds__(LBLOCK) __attribute__((amdgpu_waves_per_eu(2, 2))) void k_step_learned(
     const float* __restrict__ src, float* __restrict__ dst, Geo g, double omega, mlp::Net gnet, float threshold,
-    double* __restrict__ partials, unsigned long long* __restrict__ counts)
+    double* __restrict__ partials, unsigned long long* __restrict__ counts, float* __restrict__ ring)
 {
     __shared__ LearnedLds S;
-    learned_tiles<L, COMP, AUDIT, false, FP8>(S, gnet, src, dst, g, (float)omega, threshold, partials, counts);
+    learned_tiles<L, COMP, AUDIT, false, FP8>(S, gnet, src, dst, g, (float)omega, threshold, partials, counts, ring);
 }
 
 // In-place learned collide on the current buffer (same walk).
 template <class L, bool COMP, bool FP8>
 __global__ __launch_bounds__(LBLOCK) __attribute__((amdgpu_waves_per_eu(2, 2))) void k_collide_learned(
     float* __restrict__ buf, Geo g, double omega, mlp::Net gnet, float threshold,
-    unsigned long long* __restrict__ counts)
+    unsigned long long* __restrict__ counts, float* __restrict__ ring)
 {
     __shared__ LearnedLds S;
-    learned_tiles<L, COMP, false, true, FP8>(S, gnet, buf, buf, g, (float)omega, threshold, nullptr, counts);
+    learned_tiles<L, COMP, false, true, FP8>(S, gnet, buf, buf, g, (float)omega, threshold, nullptr, counts, ring);
 }
 
 }  // namespace d2q37
