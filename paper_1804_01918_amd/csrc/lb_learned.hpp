@@ -201,7 +201,10 @@ __device__ inline void learned_tiles(LearnedLds& S, const mlp::Net& gnet, const 
         float gh[Q];
         const mlp::Verdict vd = mlp::learned_equilibrium(v, net, X, threshold, gh);
         const bool fb = active && vd.fallback;
-        if (active && !fb) {
+        // Fallback lanes store too, so that the tile writes whole lines (a
+        // line with masked lanes is a partial write); their batch overwrites
+        // the value later, from the ring, which also makes this safe in place.
+        if (active) {
             double d[Q];
 #pragma unroll
             for (int p = 0; p < Q; ++p) {
@@ -209,13 +212,15 @@ __device__ inline void learned_tiles(LearnedLds& S, const mlp::Net& gnet, const 
                 P::template store<L::stream_stores>(st.own(dst, p, g), p, res);
                 if constexpr (AUDIT) d[p] = (double)res;
             }
-            if constexpr (AUDIT) audit_site(d, acc);
+            if constexpr (AUDIT) {
+                if (!fb) audit_site(d, acc);
+            }
         }
         const uint64_t m = __ballot(fb);
         nfb += __popcll(m);
         nact += __popcll(__ballot(active));
-        // in place, a queued site stays untouched until its batch runs:
-        // every site writes only itself
+        // in place, every site writes only itself, and a queued site's
+        // batch reads the populations from the ring
         queue_fallback<L, COMP, AUDIT>(q, ring, qh, qn, m, fb, (uint32_t)xrow * (uint32_t)g.ly + (uint32_t)r, v, dst,
                                        g, om, acc);
         mlp::wave_sync();  // the staged rows are reused by the next tile
