@@ -67,6 +67,19 @@ def test_buffer_and_scratch_sizes():
     assert lb.scratch_bytes(1, 1) >= 5 * 8
 
 
+def test_scratch_holds_the_fallback_ring():
+    """Scratch ends with the learned collide's fallback ring: 128 slots of
+    160 bytes per wavefront, 8 wavefronts per workgroup, one workgroup per
+    512-site tile up to 256 of them."""
+    ring_wg = 8 * 128 * 160
+    assert lb.scratch_bytes(1, 1) >= ring_wg
+    assert lb.scratch_bytes(3, 1024) >= 6 * ring_wg
+    assert lb.scratch_bytes(2048, 2048) >= 256 * ring_wg
+    # capped at 256 workgroups: the ring part stops growing with the lattice
+    big, bigger = lb.scratch_bytes(2048, 2048), lb.scratch_bytes(4096, 2048)
+    assert bigger - big < 256 * ring_wg
+
+
 # Rows longer than the kernels' 32-bit in-row byte offsets can address:
 # ly * 37 * elem > 2^32 (AoS, CAoSoA) or ly * elem > 2^32 (SoA, CSoA).
 ROW_LIMIT = [
