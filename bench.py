@@ -480,7 +480,8 @@ def main():
                     help="total steps (warm-up included) of the 8192 x 8192 runs")
     ap.add_argument("--only", default=None,
                     help="precision:layout[:split][:walls], 'learned' or 'learned_fp8', to time alone")
-    ap.add_argument("--lattice", type=int, default=LX, help="with --only precision:layout: the lattice size N x N")
+    ap.add_argument("--lattice", type=int, default=LX,
+                    help="with --only: the lattice size N x N (the Rayleigh-Taylor-like state unless N is 2048)")
     ap.add_argument("--copy-bytes", type=int, default=0,
                     help="only run the library's copy kernel on buffers of this size (counter calibration)")
     ap.add_argument("--copy-reps", type=int, default=5)
@@ -530,9 +531,12 @@ def main():
         net, _ = train_network(torch, lb, train=not args.untrained)
         if args.only == "learned_fp8":
             net.set_precision("fp8")
-        dt, _ = run("f32s", "caosoa", args.steps, args.warmup, net=net,
+        # --lattice N other than 2048: the N x N Rayleigh-Taylor-like state
+        n = args.lattice
+        state = None if n == LX else (n, n, [torch.from_numpy(a).cuda() for a in inputs.rayleigh_taylor(n, n, seed=0)])
+        dt, _ = run("f32s", "caosoa", args.steps, args.warmup, net=net, state=state,
                     threshold=THRESHOLD if args.threshold is None else args.threshold)
-        print(json.dumps({"only": args.only, "mlups": nsites * args.steps / dt / 1e6,
+        print(json.dumps({"only": args.only, "lattice": [n, n], "mlups": n * n * args.steps / dt / 1e6,
                           "ms_per_step": dt / args.steps * 1e3, "fallback_fraction": counts.get("fallback_fraction")}))
         net.close()
         return
